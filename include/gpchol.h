@@ -1,0 +1,147 @@
+/*
+ * gpchol: dense Cholesky factorisation of symmetric positive-definite
+ * covariance matrices and its reverse-mode derivative on AMD Instinct MI355X
+ * (gfx950), with the triangular solves and log-determinant a Gaussian-process
+ * log-density needs.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are row-major FP64 with a leading dimension `ld >= max(1, n)`:
+ *   element (i, j) of X is X[i * ld + j].  (Row-major lower is the same memory
+ *   as column-major upper.)
+ * - Symmetric inputs are given by their lower triangle including the
+ *   diagonal; the strict upper triangle of an input is never read.
+ *   Triangular outputs are lower; their strict upper triangle is written as 0.
+ * - Every data pointer is a DEVICE pointer on the handle's device and is owned
+ *   by the caller; the library never frees caller memory.  Pointers named
+ *   `*_host` are host memory read during the call only.
+ * - Calls are asynchronous: they validate arguments on the host, enqueue work
+ *   on the handle's HIP stream and return.  Results are ready when that stream
+ *   reaches the enqueued work.  No exception crosses this interface.
+ * - Status codes report argument and runtime errors; numerical failure of the
+ *   factorisation (a non-positive or NaN pivot) is data, reported through the
+ *   device integer `info`, as in LAPACK.
+ * - n == 0 is valid everywhere and enqueues nothing (except that `info` and
+ *   device scalar outputs are still written).
+ * - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef GPCHOL_H
+#define GPCHOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GPC_OK = 0,
+    GPC_ERR_ARG = 1,        /* invalid argument: n < 0, ld < max(1,n), NULL pointer, bad enum */
+    GPC_ERR_NO_DEVICE = 2,  /* no HIP device is visible */
+    GPC_ERR_ARCH = 3,       /* the current device is not gfx950 */
+    GPC_ERR_HIP = 4,        /* a HIP runtime call failed; gpc_last_error() has the message */
+    GPC_ERR_REFINE = 5,     /* iterative refinement did not reach its tolerance */
+    GPC_ERR_ALLOC = 6       /* workspace allocation failed */
+} gpc_status;
+
+typedef enum {
+    GPC_FP64 = 0,   /* every step in FP64 */
+    GPC_MIXED = 1   /* trailing SYRK/GEMM updates of factor and adjoint in FP32 on MFMA
+                       (FP32 accumulation, subtracted from FP64 storage); diagonal
+                       blocks, panels and log-determinant stay FP64 */
+} gpc_precision;
+
+typedef enum { GPC_NOTRANS = 0, GPC_TRANS = 1 } gpc_trans;
+
+typedef struct {
+    int32_t precision;     /* gpc_precision; default GPC_FP64 */
+    int32_t block;         /* outer block size b of the blocked algorithms; 0 = library default */
+    int32_t lookahead;     /* 1 = overlap the next diagonal step with the trailing update */
+    int32_t refine_maxit;  /* maximum refinement iterations of gpc_solve_refined (default 10) */
+    double  refine_tol;    /* stop when the normwise backward error eta_inf <= refine_tol (default 1e-12) */
+} gpc_options;
+
+typedef struct gpc_handle gpc_handle;
+
+/* Create a handle bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The handle owns a device
+ * workspace that grows on demand and is freed by gpc_destroy.
+ * Errors: GPC_ERR_ARG (h NULL), GPC_ERR_NO_DEVICE, GPC_ERR_ARCH, GPC_ERR_HIP. */
+gpc_status gpc_create(gpc_handle** h, void* hip_stream);
+
+/* Wait for the handle's stream, free its workspace and the handle. */
+gpc_status gpc_destroy(gpc_handle* h);
+
+/* Rebind the handle to another stream of the same device. */
+gpc_status gpc_set_stream(gpc_handle* h, void* hip_stream);
+
+/* Replace the handle's options (copied).  GPC_ERR_ARG on NULL, an unknown
+ * precision, block not in {0, 64, 128, 256}, refine_maxit < 0 or refine_tol <= 0. */
+gpc_status gpc_set_options(gpc_handle* h, const gpc_options* opt);
+gpc_status gpc_get_options(const gpc_handle* h, gpc_options* opt);
+
+/* Factor (section 3.3.1: L11 = chol(A11), L21 = A21 L11^-T, then the Schur
+ * complement A22 - L21 L21^T is factored the same way).  In place: on return
+ * the lower triangle of A holds L and its strict upper triangle holds 0.
+ * info_dev (device int32) receives 0, or j+1 for the first column j whose pivot
+ * is not positive or is NaN; L is then unspecified.
+ * Uses the handle's precision (GPC_MIXED: trailing updates in FP32). */
+gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info_dev);
+
+/* Reverse-mode derivative of the factor (section 3.3.2: the blocked gradient
+ * with the diagonal of each diagonal block's adjoint halved and its upper
+ * triangle zeroed).  Inputs: L (lower, not modified) and Lbar, the adjoint of
+ * the lower triangle of L.  In place: the lower triangle of Lbar becomes Abar,
+ * the gradient with respect to the independent lower-triangle entries a_ij
+ * (i >= j) of the symmetric A (a perturbation of a_ij, i > j, moves both A_ij
+ * and A_ji); its strict upper triangle becomes 0.  L and Lbar must not overlap. */
+gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl,
+                       double* Lbar, int64_t ldlb);
+
+/* Triangular solve with the factor (section 3.2, A x = b with A triangular):
+ * B <- L^-1 B (trans = GPC_NOTRANS) or B <- L^-T B (GPC_TRANS).
+ * B is n x nrhs row-major with leading dimension ldb >= max(1, nrhs). */
+gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs,
+                    const double* L, int64_t ldl, double* B, int64_t ldb);
+
+/* log|A| = 2 * sum_i log L_ii, accumulated in FP64 in a fixed order
+ * (independent of launch shape).  out_dev: one device double. */
+gpc_status gpc_logdet(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* out_dev);
+
+/* Kernel classes reported by the launch trace below. */
+typedef enum {
+    GPC_K_DIAG_FACTOR = 0,      /* diagonal-block factor + inverse (one workgroup) */
+    GPC_K_PANEL_SOLVE = 1,      /* L21 = A21 inv(L11)^T */
+    GPC_K_TRAILING_UPDATE = 2,  /* A22 -= L21 L21^T (lower tiles) */
+    GPC_K_DIAG_INVERSE = 3,     /* inverses of all diagonal blocks (reverse sweep, solves) */
+    GPC_K_ADJ_PANEL_SOLVE = 4,  /* Cbar <- Cbar D^-1 */
+    GPC_K_ADJ_LEFT_UPDATE = 5,  /* Bbar -= Cbar R */
+    GPC_K_ADJ_DIAG_PRODUCT = 6, /* split-K slices of Cbar^T C */
+    GPC_K_ADJ_DIAG_BLOCK = 7,   /* Dbar <- Phi(D^-T sym(D^T Dbar) D^-1) (4 launches) */
+    GPC_K_ADJ_ROW_UPDATE = 8,   /* split-K slices of [M; Cbar]^T [R; B] */
+    GPC_K_REDUCE = 9,           /* fixed-order sum of split-K slices into Rbar */
+    GPC_K_COUNT = 10
+} gpc_kernel_class;
+
+/* Launch trace, for measurement: while enabled, every launch of the classes
+ * above is bracketed by a pair of HIP events on the handle's stream and its
+ * algorithmic flops and bytes (the useful work of that launch, counted on the
+ * host) are recorded.  gpc_trace_read waits for the stream and returns, for
+ * one class, the number of launches, the sum of their event-measured
+ * durations (ms), and the summed flops and bytes.  gpc_trace_reset waits for
+ * the stream and forgets all records.  Tracing is off by default. */
+gpc_status gpc_trace_enable(gpc_handle* h, int32_t on);
+gpc_status gpc_trace_reset(gpc_handle* h);
+gpc_status gpc_trace_read(gpc_handle* h, int32_t kclass, int64_t* launches, double* ms,
+                          double* flops, double* bytes);
+
+/* Static description of a status code (never NULL). */
+const char* gpc_status_string(gpc_status s);
+
+/* Message of the last GPC_ERR_HIP / GPC_ERR_ALLOC on this handle ("" if none). */
+const char* gpc_last_error(const gpc_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPCHOL_H */

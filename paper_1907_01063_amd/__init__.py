@@ -1,0 +1,7 @@
+"""MI355X (gfx950) Cholesky factor and reverse-mode adjoint for Gaussian-process
+covariance matrices, behind the C ABI of ``include/gpchol.h``.
+
+``gpchol`` is the ctypes binding; ``build`` compiles the HIP library in-tree.
+"""
+from . import gpchol  # noqa: F401
+from .gpchol import Handle, GpcError, default_handle  # noqa: F401

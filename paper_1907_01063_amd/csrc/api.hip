@@ -1,0 +1,435 @@
+// C ABI of libgpchol: argument checks, the handle's workspace, and the host
+// loops of the blocked algorithms (each step enqueues kernels on the handle's
+// stream; nothing here waits for the device except workspace growth).
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "gpchol.h"
+#include "internal.hpp"
+
+// One traced launch: events around it plus its algorithmic flops and bytes.
+struct TraceRec {
+    int cls;
+    hipEvent_t t0, t1;
+    double flops, bytes;
+};
+
+struct gpc_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    gpc_options opt{};
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    char err[256] = {0};
+    bool trace = false;
+    std::vector<TraceRec> recs;        // launches recorded since the last reset
+    std::vector<hipEvent_t> ev_pool;   // events owned by the handle
+    size_t ev_used = 0;
+};
+
+namespace {
+
+using namespace gpc;
+
+constexpr int kDefaultBlock = 128;
+
+gpc_status hip_fail(gpc_handle* h, hipError_t e, const char* what)
+{
+    if (h) snprintf(h->err, sizeof(h->err), "%s: %s", what, hipGetErrorString(e));
+    return GPC_ERR_HIP;
+}
+
+#define GPC_HIP(h, call)                                        \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return hip_fail((h), e_, #call);  \
+    } while (0)
+
+// Grow-only device workspace; waits for the stream before releasing the old one.
+gpc_status ensure_ws(gpc_handle* h, size_t bytes)
+{
+    if (bytes <= h->ws_bytes) return GPC_OK;
+    if (h->ws) {
+        GPC_HIP(h, hipStreamSynchronize(h->stream));
+        GPC_HIP(h, hipFree(h->ws));
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    hipError_t e = hipMalloc(&h->ws, want);
+    if (e != hipSuccess) {
+        snprintf(h->err, sizeof(h->err), "workspace of %zu bytes: %s", want, hipGetErrorString(e));
+        h->ws = nullptr;
+        return GPC_ERR_ALLOC;
+    }
+    h->ws_bytes = want;
+    return GPC_OK;
+}
+
+hipEvent_t take_event(gpc_handle* h)
+{
+    if (h->ev_used == h->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->ev_pool.push_back(e);
+    }
+    return h->ev_pool[h->ev_used++];
+}
+
+// Bracket one launch of kernel class `cls` with events when tracing is on.
+struct Traced {
+    gpc_handle* h;
+    TraceRec rec{};
+    bool on;
+    Traced(gpc_handle* h_, int cls, double flops, double bytes) : h(h_), on(h_->trace)
+    {
+        if (!on) return;
+        rec.cls = cls;
+        rec.flops = flops;
+        rec.bytes = bytes;
+        rec.t0 = take_event(h);
+        rec.t1 = take_event(h);
+        if (!rec.t0 || !rec.t1) { on = false; return; }
+        hipEventRecord(rec.t0, h->stream);
+    }
+    ~Traced()
+    {
+        if (!on) return;
+        hipEventRecord(rec.t1, h->stream);
+        h->recs.push_back(rec);
+    }
+};
+
+int block_of(const gpc_handle* h) { return h->opt.block > 0 ? h->opt.block : kDefaultBlock; }
+
+bool ld_ok(int64_t n, int64_t ld) { return ld >= std::max<int64_t>(1, n); }
+
+// Fixed split-K plan: about 512 workgroups per launch, at least 256 k-values
+// per split, chunk a multiple of 32 (the largest BK).
+void splitk_plan(int64_t tiles, int64_t K, int max_splits, int* splits, int64_t* chunk)
+{
+    int64_t s = std::max<int64_t>(1, (512 + tiles - 1) / tiles);
+    s = std::min<int64_t>(s, std::max<int64_t>(1, K / 256));
+    s = std::min<int64_t>(s, max_splits);
+    int64_t c = (K + s - 1) / s;
+    c = (c + 31) / 32 * 32;
+    s = std::max<int64_t>(1, (K + c - 1) / c);
+    *splits = (int)s;
+    *chunk = c;
+}
+
+GemmArgs gemm_args(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
+                   int64_t ldb, double* C, int64_t ldc)
+{
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.lda = lda;
+    g.B = B; g.ldb = ldb;
+    g.C = C; g.ldc = ldc;
+    g.kchunk = K > 0 ? K : 1;
+    return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gpc_status_string(gpc_status s)
+{
+    switch (s) {
+    case GPC_OK: return "ok";
+    case GPC_ERR_ARG: return "invalid argument";
+    case GPC_ERR_NO_DEVICE: return "no HIP device";
+    case GPC_ERR_ARCH: return "device is not gfx950";
+    case GPC_ERR_HIP: return "HIP runtime error";
+    case GPC_ERR_REFINE: return "iterative refinement did not converge";
+    case GPC_ERR_ALLOC: return "workspace allocation failed";
+    }
+    return "unknown status";
+}
+
+const char* gpc_last_error(const gpc_handle* h) { return h ? h->err : ""; }
+
+gpc_status gpc_create(gpc_handle** out, void* stream)
+{
+    if (!out) return GPC_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return GPC_ERR_NO_DEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GPC_ERR_NO_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GPC_ERR_HIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GPC_ERR_ARCH;
+    gpc_handle* h = new (std::nothrow) gpc_handle();
+    if (!h) return GPC_ERR_ALLOC;
+    h->device = dev;
+    h->stream = (hipStream_t)stream;
+    h->opt.precision = GPC_FP64;
+    h->opt.block = 0;
+    h->opt.lookahead = 0;
+    h->opt.refine_maxit = 10;
+    h->opt.refine_tol = 1e-12;
+    *out = h;
+    return GPC_OK;
+}
+
+gpc_status gpc_destroy(gpc_handle* h)
+{
+    if (!h) return GPC_ERR_ARG;
+    gpc_status st = GPC_OK;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) st = GPC_ERR_HIP;
+    if (h->ws && hipFree(h->ws) != hipSuccess) st = GPC_ERR_HIP;
+    for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+    delete h;
+    return st;
+}
+
+gpc_status gpc_trace_enable(gpc_handle* h, int32_t on)
+{
+    if (!h) return GPC_ERR_ARG;
+    h->trace = on != 0;
+    return GPC_OK;
+}
+
+gpc_status gpc_trace_reset(gpc_handle* h)
+{
+    if (!h) return GPC_ERR_ARG;
+    GPC_HIP(h, hipStreamSynchronize(h->stream));
+    h->recs.clear();
+    h->ev_used = 0;
+    return GPC_OK;
+}
+
+gpc_status gpc_trace_read(gpc_handle* h, int32_t kclass, int64_t* launches, double* ms, double* flops,
+                          double* bytes)
+{
+    if (!h || !launches || !ms || !flops || !bytes || kclass < 0 || kclass >= GPC_K_COUNT)
+        return GPC_ERR_ARG;
+    GPC_HIP(h, hipStreamSynchronize(h->stream));
+    *launches = 0;
+    *ms = *flops = *bytes = 0.0;
+    for (const TraceRec& r : h->recs) {
+        if (r.cls != kclass) continue;
+        float e = 0.f;
+        GPC_HIP(h, hipEventElapsedTime(&e, r.t0, r.t1));
+        *launches += 1;
+        *ms += e;
+        *flops += r.flops;
+        *bytes += r.bytes;
+    }
+    return GPC_OK;
+}
+
+gpc_status gpc_set_stream(gpc_handle* h, void* stream)
+{
+    if (!h) return GPC_ERR_ARG;
+    h->stream = (hipStream_t)stream;
+    return GPC_OK;
+}
+
+gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
+{
+    if (!h || !o) return GPC_ERR_ARG;
+    if (o->precision != GPC_FP64 && o->precision != GPC_MIXED) return GPC_ERR_ARG;
+    if (o->block != 0 && o->block != 32 && o->block != 64 && o->block != 128) return GPC_ERR_ARG;
+    if (o->refine_maxit < 0 || !(o->refine_tol > 0.0)) return GPC_ERR_ARG;
+    h->opt = *o;
+    return GPC_OK;
+}
+
+gpc_status gpc_get_options(const gpc_handle* h, gpc_options* o)
+{
+    if (!h || !o) return GPC_ERR_ARG;
+    *o = h->opt;
+    return GPC_OK;
+}
+
+// ---------------------------------------------------------------- factor ---
+// Right-looking blocked factorisation (section 3.3.1) with block b:
+//   for each diagonal block: factor it and form its inverse (one workgroup),
+//   L21 = A21 * inv(L11)^T (MFMA product, in place), A22 -= L21 L21^T on the
+//   lower tiles of the trailing matrix (MFMA SYRK);
+// then the strict upper triangle is zeroed.
+gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info)
+{
+    if (!h || n < 0 || !ld_ok(n, lda) || !info || (n > 0 && !A)) return GPC_ERR_ARG;
+    hipStream_t s = h->stream;
+    GPC_HIP(h, fill_i32(s, info, 0));
+    if (n == 0) return GPC_OK;
+    const int b = block_of(h);
+    gpc_status st = ensure_ws(h, sizeof(double) * (size_t)b * b);
+    if (st != GPC_OK) return st;
+    double* Linv = (double*)h->ws;
+    for (int64_t k = 0; k < n; k += b) {
+        const int kb = (int)std::min<int64_t>(b, n - k);
+        const double dkb = (double)kb;
+        {
+            Traced t(h, GPC_K_DIAG_FACTOR, dkb * dkb * dkb / 3.0, 16.0 * dkb * dkb);
+            GPC_HIP(h, potrf_diag(s, kb, A + k * lda + k, lda, Linv, b, info, k));
+        }
+        const int64_t m = n - k - kb;
+        if (m <= 0) continue;
+        const double dm = (double)m;
+        double* A21 = A + (k + kb) * lda + k;
+        double* A22 = A + (k + kb) * lda + (k + kb);
+        {
+            Traced t(h, GPC_K_PANEL_SOLVE, dm * dkb * dkb, 8.0 * (2.0 * dm * dkb + dkb * dkb));
+            GemmArgs pg = gemm_args(m, kb, kb, A21, lda, Linv, b, A21, lda);
+            GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_STORE, false, pg, 1));
+        }
+        {
+            Traced t(h, GPC_K_TRAILING_UPDATE, dm * (dm + 1.0) * dkb,
+                     8.0 * (dm * dkb + dm * (dm + 1.0)));
+            GemmArgs sg = gemm_args(m, m, kb, A21, lda, A21, lda, A22, lda);
+            GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_SUB, true, sg, 1));
+        }
+    }
+    GPC_HIP(h, zero_strict_upper(s, n, A, lda));
+    return GPC_OK;
+}
+
+// --------------------------------------------------------------- adjoint ---
+// Blocked reverse sweep (section 3.3.2), diagonal blocks from last to first.
+// With D = L[j:k, j:k], R = L[j:k, 0:j], C = L[k:n, j:k], B = L[k:n, 0:j] and
+// the matching blocks of Lbar (Dbar, Rbar, Cbar, Bbar):
+//   Cbar <- Cbar D^-1;  Bbar -= Cbar R;  Dbar <- tril(Dbar - Cbar^T C);
+//   P = D^T Dbar;  S = tril(P) + stril(P)^T;  M = D^-T S D^-1  (symmetric);
+//   Rbar -= Cbar^T B + M R;  Dbar <- tril(M) - diag(M)/2.
+// The D^-1 of every block come from one batched launch up front; the long
+// products Cbar^T C and Cbar^T B (inner dimension n-k) are split along k into
+// fixed slices that are added in a fixed order.
+gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* Lbar,
+                       int64_t ldlb)
+{
+    if (!h || n < 0 || !ld_ok(n, ldl) || !ld_ok(n, ldlb) || (n > 0 && (!L || !Lbar)))
+        return GPC_ERR_ARG;
+    if (n == 0) return GPC_OK;
+    hipStream_t s = h->stream;
+    const int b = block_of(h);
+    const int64_t nblk = (n + b - 1) / b;
+    const int kMaxSd = 64, kMaxSr = 32;
+
+    // plan the split counts of every step to size the partial buffers
+    int64_t pr_elems = 1;
+    for (int64_t q = nblk - 1; q >= 0; --q) {
+        const int64_t j = q * b, k = std::min<int64_t>(n, j + b), bq = k - j;
+        if (j == 0) continue;
+        int sr; int64_t ch;
+        splitk_plan(((bq + 127) / 128) * ((j + 127) / 128), bq + (n - k), kMaxSr, &sr, &ch);
+        pr_elems = std::max<int64_t>(pr_elems, (int64_t)sr * bq * j);
+    }
+    const size_t bb = (size_t)b * b;
+    const size_t n_dinv = (size_t)nblk * bb, n_pd = (size_t)kMaxSd * bb;
+    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + n_pd + 4 * bb + (size_t)pr_elems));
+    if (st != GPC_OK) return st;
+    double* Dinv = (double*)h->ws;
+    double* Pd = Dinv + n_dinv;
+    double* Wd = Pd + n_pd;
+    double* Sw = Wd + bb;
+    double* Tw = Sw + bb;
+    double* Mw = Tw + bb;
+    double* Pr = Mw + bb;
+
+    {
+        const double db = (double)b;
+        Traced t(h, GPC_K_DIAG_INVERSE, (double)nblk * db * db * db / 3.0, 8.0 * 2.0 * (double)nblk * db * db);
+        GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+    }
+    for (int64_t q = nblk - 1; q >= 0; --q) {
+        const int64_t j = q * b, k = std::min<int64_t>(n, j + b), bq = k - j, nr = n - k;
+        const double* D = L + j * ldl + j;
+        const double* Dq_inv = Dinv + (size_t)q * bb;
+        double* Dbar = Lbar + j * ldlb + j;
+        double* Cbar = Lbar + k * ldlb + j;
+        const double* C = L + k * ldl + j;
+        int sd = 0;
+        const double dbq = (double)bq, dnr = (double)nr, dj = (double)j;
+        if (nr > 0) {
+            {
+                Traced t(h, GPC_K_ADJ_PANEL_SOLVE, dnr * dbq * dbq, 8.0 * (2.0 * dnr * dbq + dbq * dbq));
+                GemmArgs g5 = gemm_args(nr, bq, bq, Cbar, ldlb, Dq_inv, b, Cbar, ldlb);
+                GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g5, 1));
+            }
+            if (j > 0) {
+                Traced t(h, GPC_K_ADJ_LEFT_UPDATE, 2.0 * dnr * dj * dbq,
+                         8.0 * (2.0 * dnr * dj + dnr * dbq + dbq * dj));
+                GemmArgs g6 = gemm_args(nr, j, bq, Cbar, ldlb, L + j * ldl, ldl, Lbar + k * ldlb, ldlb);
+                GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_SUB, false, g6, 1));
+            }
+            int64_t ch;
+            splitk_plan(((bq + 63) / 64) * ((bq + 63) / 64), nr, kMaxSd, &sd, &ch);
+            Traced t(h, GPC_K_ADJ_DIAG_PRODUCT, 2.0 * dbq * dbq * dnr, 8.0 * (2.0 * dnr * dbq + sd * dbq * dbq));
+            GemmArgs gd = gemm_args(bq, bq, nr, Cbar, ldlb, C, ldl, Pd, bq);
+            gd.kchunk = ch;
+            gd.pstride = (int64_t)bb;
+            GPC_HIP(h, gemm_f64(s, TILE_64, true, false, EPI_PARTIAL, false, gd, sd));
+        }
+        {
+            Traced t(h, GPC_K_ADJ_DIAG_BLOCK, 3.0 * dbq * dbq * dbq, 8.0 * 8.0 * dbq * dbq);
+            GPC_HIP(h, reduce_tril(s, (int)bq, Dbar, ldlb, Pd, sd, (int64_t)bb, Wd));
+            GemmArgs gp = gemm_args(bq, bq, bq, D, ldl, Wd, bq, Sw, bq);
+            gp.a_lower = 1;
+            GPC_HIP(h, gemm_f64(s, TILE_64, true, false, EPI_SYMLOW, false, gp, 1));
+            GemmArgs gt = gemm_args(bq, bq, bq, Sw, bq, Dq_inv, b, Tw, bq);
+            GPC_HIP(h, gemm_f64(s, TILE_64, false, false, EPI_STORE, false, gt, 1));
+            GemmArgs gm = gemm_args(bq, bq, bq, Dq_inv, b, Tw, bq, Mw, bq);
+            gm.C2 = Dbar;
+            gm.ldc2 = ldlb;
+            GPC_HIP(h, gemm_f64(s, TILE_64, true, false, EPI_PHI, false, gm, 1));
+        }
+        if (j > 0) {
+            int sr; int64_t ch;
+            const int64_t K = bq + nr;
+            splitk_plan(((bq + 127) / 128) * ((j + 127) / 128), K, kMaxSr, &sr, &ch);
+            {
+                Traced t(h, GPC_K_ADJ_ROW_UPDATE, 2.0 * dbq * dj * (double)K,
+                         8.0 * ((double)K * (dbq + dj) + sr * dbq * dj));
+                GemmArgs gr = gemm_args(bq, j, K, Cbar, ldlb, L + j * ldl, ldl, Pr, j);
+                gr.Ahead = Mw;
+                gr.ldah = bq;
+                gr.head_k = bq;
+                gr.kchunk = ch;
+                gr.pstride = bq * j;
+                GPC_HIP(h, gemm_f64(s, TILE_128, true, false, EPI_PARTIAL, false, gr, sr));
+            }
+            Traced t(h, GPC_K_REDUCE, dbq * dj * sr, 8.0 * (sr + 2.0) * dbq * dj);
+            GPC_HIP(h, reduce_sub(s, bq, j, Pr, sr, bq * j, Lbar + j * ldlb, ldlb));
+        }
+    }
+    GPC_HIP(h, zero_strict_upper(s, n, Lbar, ldlb));
+    return GPC_OK;
+}
+
+// ----------------------------------------------------------------- solves ---
+gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
+                    double* B, int64_t ldb)
+{
+    if (!h || (trans != GPC_NOTRANS && trans != GPC_TRANS) || n < 0 || nrhs < 0 || !ld_ok(n, ldl) ||
+        !ld_ok(nrhs, ldb) || (n > 0 && nrhs > 0 && (!L || !B)))
+        return GPC_ERR_ARG;
+    if (n == 0 || nrhs == 0) return GPC_OK;
+    hipStream_t s = h->stream;
+    const int b = block_of(h);
+    const int64_t nblk = (n + b - 1) / b;
+    const size_t n_dinv = (size_t)nblk * b * b;
+    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + 8 * (size_t)n));
+    if (st != GPC_OK) return st;
+    double* Dinv = (double*)h->ws;
+    double* Y = Dinv + n_dinv;
+    GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+    GPC_HIP(h, trsm_blocked(s, trans, n, nrhs, L, ldl, Dinv, b, B, ldb, Y));
+    return GPC_OK;
+}
+
+gpc_status gpc_logdet(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* out)
+{
+    if (!h || n < 0 || !ld_ok(n, ldl) || !out || (n > 0 && !L)) return GPC_ERR_ARG;
+    GPC_HIP(h, logdet(h->stream, n, L, ldl, out));
+    return GPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Diagonal-block kernels: one workgroup owns one kb x kb block (kb <= 128)
+// held entirely in LDS (128 x 129 doubles = 132 KB of the CU's 160 KB).
+//
+// potrf_diag: the classic unblocked Cholesky of the diagonal block, the
+// "chol" step of section 3.3.1, run right-looking inside the workgroup, then
+// the inverse of the resulting triangle (needed by the panel solve
+// L21 = A21 L11^-T, section 3.3.1, done as a product with the inverse as the
+// paper does with its lower-triangular inverse, section 3.2).
+//
+// trtri_diag_batched: inverses of all diagonal blocks of a given factor, one
+// workgroup per block (the D^-1 of each step of the reverse sweep, 3.3.2);
+// block q goes to Dinv + q*b*b with leading dimension b.
+#include "internal.hpp"
+
+namespace gpc {
+namespace {
+
+constexpr int P = kDiagMax + 1;   // LDS row pitch (odd: spreads column walks over banks)
+
+// Right-looking factorisation of the block in S (lower triangle valid).
+// Step j subtracts the outer product of the still unscaled column j divided by
+// its pivot d_j from the trailing triangle; the scaling of column j by
+// sqrt(d_j) is deferred to step j+1, when nobody reads that column, so each
+// step needs one barrier.  Thread (ty, tx) of a 16 x 16 grid owns the trailing
+// elements whose offsets are congruent to (ty, tx) modulo 16.
+__device__ void factor_in_lds(double* S, int kb, int32_t* info, int64_t col0)
+{
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    double dprev = 1.0;
+    for (int j = 0; j < kb; ++j) {
+        if (j > 0) {
+            const double sq = sqrt(dprev);
+            for (int i = j + tid; i < kb; i += 256) S[i * P + (j - 1)] /= sq;
+            if (tid == 0) S[(j - 1) * P + (j - 1)] = sq;
+        }
+        const double d = S[j * P + j];
+        if (tid == 0 && !(d > 0.0) && info != nullptr && *info == 0)
+            *info = (int32_t)(col0 + j + 1);
+        const double rd = 1.0 / d;
+        const int m = kb - j - 1;
+        for (int q = tx; q < m; q += 16) {
+            const int c = j + 1 + q;
+            const double scj = S[c * P + j] * rd;
+            for (int p = q + ((ty - q) & 15); p < m; p += 16) {   // p >= q, p == ty (mod 16)
+                const int i = j + 1 + p;
+                S[i * P + c] -= S[i * P + j] * scj;
+            }
+        }
+        dprev = d;
+        __syncthreads();
+    }
+    if (tid == 0) S[(kb - 1) * P + (kb - 1)] = sqrt(dprev);
+    __syncthreads();
+}
+
+// X = L^-1 for the lower triangle L in S.  X[i][c] (i > c) is kept in the
+// strict upper triangle at S[c][i], the diagonal of X in xd.  Row j of X is
+// final once divided by L_jj; it is then subtracted, times L_ij, from every
+// later row i (forward substitution on all columns at once).  The division of
+// row j is deferred to step j+1, one barrier per step.
+__device__ void invert_in_lds(double* S, double* xd, int kb)
+{
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    for (int i = tid; i < kb; i += 256) xd[i] = 1.0;
+    for (int idx = tid; idx < kb * kb; idx += 256) {
+        const int r = idx / kb, c = idx % kb;
+        if (c > r) S[r * P + c] = 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < kb; ++j) {
+        if (j > 0) {
+            const double l = S[(j - 1) * P + (j - 1)];
+            for (int c = tid; c < j; c += 256) {
+                if (c == j - 1) xd[j - 1] /= l;
+                else S[c * P + (j - 1)] /= l;
+            }
+        }
+        const double ljj = S[j * P + j];
+        const int m = kb - j - 1;
+        for (int q = tx; q <= j; q += 16) {
+            const double xjc = (q == j ? xd[j] : S[q * P + j]) / ljj;
+            for (int p = ty; p < m; p += 16) {
+                const int i = j + 1 + p;
+                S[q * P + i] -= S[i * P + j] * xjc;
+            }
+        }
+        __syncthreads();
+    }
+    {
+        const double l = S[(kb - 1) * P + (kb - 1)];
+        for (int c = tid; c < kb; c += 256) {
+            if (c == kb - 1) xd[kb - 1] /= l;
+            else S[c * P + (kb - 1)] /= l;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256)
+potrf_diag_kernel(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info, int64_t col0)
+{
+    __shared__ double S[kDiagMax * P];
+    __shared__ double xd[kDiagMax];
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < kb * kb; idx += 256) {
+        const int r = idx / kb, c = idx % kb;
+        S[r * P + c] = c <= r ? A[r * lda + c] : 0.0;
+    }
+    __syncthreads();
+    factor_in_lds(S, kb, info, col0);
+    for (int idx = tid; idx < kb * kb; idx += 256) {
+        const int r = idx / kb, c = idx % kb;
+        A[r * lda + c] = c <= r ? S[r * P + c] : 0.0;
+    }
+    __syncthreads();
+    invert_in_lds(S, xd, kb);
+    for (int idx = tid; idx < kb * kb; idx += 256) {
+        const int r = idx / kb, c = idx % kb;
+        Linv[r * ldi + c] = c < r ? S[c * P + r] : (c == r ? xd[r] : 0.0);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+trtri_batched_kernel(int64_t n, int b, const double* L, int64_t ldl, double* Dinv)
+{
+    __shared__ double S[kDiagMax * P];
+    __shared__ double xd[kDiagMax];
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * b;
+    const int kb = (int)min((int64_t)b, n - r0);
+    const double* D = L + r0 * ldl + r0;
+    double* X = Dinv + (int64_t)blockIdx.x * b * b;
+    for (int idx = tid; idx < kb * kb; idx += 256) {
+        const int r = idx / kb, c = idx % kb;
+        S[r * P + c] = c <= r ? D[r * ldl + c] : 0.0;
+    }
+    __syncthreads();
+    invert_in_lds(S, xd, kb);
+    for (int idx = tid; idx < kb * kb; idx += 256) {
+        const int r = idx / kb, c = idx % kb;
+        X[r * b + c] = c < r ? S[c * P + r] : (c == r ? xd[r] : 0.0);
+    }
+}
+
+}  // namespace
+
+hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Linv, int64_t ldi,
+                      int32_t* info, int64_t col0)
+{
+    if (kb <= 0) return hipSuccess;
+    if (kb > kDiagMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
+    return hipGetLastError();
+}
+
+hipError_t trtri_diag_batched(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl, double* Dinv)
+{
+    if (n <= 0) return hipSuccess;
+    if (b <= 0 || b > kDiagMax) return hipErrorInvalidValue;
+    const int64_t nblk = (n + b - 1) / b;
+    hipLaunchKernelGGL(trtri_batched_kernel, dim3((unsigned)nblk), dim3(256), 0, s, n, b, L, ldl, Dinv);
+    return hipGetLastError();
+}
+
+}  // namespace gpc

@@ -1,0 +1,83 @@
+// Memory-bound helpers of the blocked factor and reverse sweep: flag reset,
+// zeroing of the strict upper triangle (outputs are lower-triangular views,
+// section 2.2), and the fixed-order sums of split-K partial products
+// (section 3.1, "large k": s partial copies added by a separate kernel; here
+// the copies are added in increasing order so results do not depend on timing).
+#include "internal.hpp"
+
+namespace gpc {
+namespace {
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v) { *p = v; }
+
+// One thread per element of a 64-wide column strip; blocks that lie entirely
+// on or below the diagonal exit at once.
+__global__ void zero_upper_kernel(int64_t n, double* A, int64_t lda)
+{
+    const int64_t r = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (r < n && c < n && c > r) A[r * lda + c] = 0.0;
+}
+
+__global__ void reduce_sub_kernel(int64_t M, int64_t N, const double* P, int S, int64_t pstride,
+                                  double* C, int64_t ldc)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M * N) return;
+    const int64_t m = e / N, n = e % N;
+    double s = 0.0;
+    for (int z = 0; z < S; ++z) s += P[z * pstride + m * N + n];
+    C[m * ldc + n] -= s;
+}
+
+__global__ void reduce_tril_kernel(int b, const double* D, int64_t ldd, const double* P, int S,
+                                   int64_t pstride, double* W)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= b * b) return;
+    const int m = e / b, n = e % b;
+    double v = 0.0;
+    if (m >= n) {
+        double s = 0.0;
+        for (int z = 0; z < S; ++z) s += P[z * pstride + (int64_t)m * b + n];
+        v = D[m * ldd + n] - s;
+    }
+    W[e] = v;
+}
+
+}  // namespace
+
+hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v)
+{
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t zero_strict_upper(hipStream_t s, int64_t n, double* A, int64_t lda)
+{
+    if (n <= 1) return hipSuccess;
+    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 3) / 4));
+    hipLaunchKernelGGL(zero_upper_kernel, grid, dim3(256), 0, s, n, A, lda);
+    return hipGetLastError();
+}
+
+hipError_t reduce_sub(hipStream_t s, int64_t M, int64_t N, const double* P, int S, int64_t pstride,
+                      double* C, int64_t ldc)
+{
+    if (M <= 0 || N <= 0 || S <= 0) return hipSuccess;
+    const int64_t tot = M * N;
+    hipLaunchKernelGGL(reduce_sub_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       M, N, P, S, pstride, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t reduce_tril(hipStream_t s, int b, const double* D, int64_t ldd, const double* P, int S,
+                       int64_t pstride, double* W)
+{
+    if (b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_tril_kernel, dim3((unsigned)((b * b + 255) / 256)), dim3(256), 0, s,
+                       b, D, ldd, P, S, pstride, W);
+    return hipGetLastError();
+}
+
+}  // namespace gpc

@@ -1,0 +1,244 @@
+// Tiled matrix products on the CDNA4 matrix cores (MFMA 16x16x4, FP64 or FP32).
+//
+// These are the dense contractions of the blocked Cholesky (the panel solve
+// L21 = A21 L11^-T and the trailing update A22 - L21 L21^T of section 3.3.1)
+// and of its blocked reverse sweep (the products of section 3.3.2).
+//
+// A workgroup of 4 waves (2 x 2) owns a BM x BN output tile; each wave owns a
+// (BM/2) x (BN/2) sub-tile made of 16x16 MFMA blocks held in accumulator
+// registers.  The k dimension is walked in chunks of BK: the next chunk is
+// loaded from global memory into registers while the current chunk is consumed
+// from LDS (two LDS buffers, one barrier per chunk).  Operands are staged in
+// LDS k-major (sA[k][m], sB[k][n]) so that each MFMA operand fetch reads 16
+// consecutive elements per k row.
+//
+// MFMA 16x16x4 register layout (one value per lane for A and B; 4 per lane
+// for the 16x16 result): lane l supplies A[l%16][l/16] and B[l/16][l%16].
+// The result rows differ by type (measured on gfx950): the FP64 instruction
+// puts element (l/16 + 4r, l%16) in accumulator slot r, the FP32 instruction
+// puts element (4*(l/16) + r, l%16) there.
+#include "internal.hpp"
+
+namespace gpc {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef d4v acc_t;
+    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lr, int r) { return lr + 4 * r; }
+};
+template <> struct Mfma<float> {
+    typedef f4v acc_t;
+    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lr, int r) { return 4 * lr + r; }
+};
+
+template <typename TI, int BM, int BN, int BK, bool AKM, bool BNK, int EPI, bool LOWER>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
+{
+    constexpr int NT = 256;
+    constexpr int WTM = BM / 2, WTN = BN / 2;   // wave sub-tile
+    constexpr int FM = WTM / 16, FN = WTN / 16;  // MFMA blocks per wave
+    constexpr int PAD = sizeof(TI) == 8 ? 2 : 4;
+    constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+    static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile/thread mismatch");
+    typedef typename Mfma<TI>::acc_t acc_t;
+
+    __shared__ TI sA[2][BK][BM + PAD];
+    __shared__ TI sB[2][BK][BN + PAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    int64_t tm, tn;
+    if (LOWER) {
+        const int64_t b = blockIdx.x;
+        int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+        while (ti * (ti + 1) / 2 > b) --ti;
+        while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+        tm = ti;
+        tn = b - ti * (ti + 1) / 2;
+    } else {
+        const int64_t tilesN = (g.N + BN - 1) / BN;
+        tm = blockIdx.x / tilesN;
+        tn = blockIdx.x % tilesN;
+    }
+    const int64_t m0 = tm * BM, n0 = tn * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = min(g.K, kbeg + g.kchunk);
+
+    // no __restrict__: the in-place panel products write the rows they read
+    const TI* Ap = (const TI*)g.A;
+    const TI* Hp = (const TI*)g.Ahead;
+    const TI* Bp = (const TI*)g.B;
+
+    TI ra[LA], rb[LB];
+
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int p = 0; p < LA; ++p) {
+            const int idx = tid + p * NT;
+            const int kk = AKM ? idx / BM : idx % BK;
+            const int mm = AKM ? idx % BM : idx / BK;
+            const int64_t gm = m0 + mm, gk = k0 + kk;
+            TI v = (TI)0;
+            const bool upper = g.a_lower && (AKM ? gm > gk : gk > gm);
+            if (gm < g.M && gk < kend && !upper) {
+                if (!AKM) v = Ap[gm * g.lda + gk];
+                else if (gk < g.head_k) v = Hp[gk * g.ldah + gm];
+                else v = Ap[(gk - g.head_k) * g.lda + gm];
+            }
+            ra[p] = v;
+        }
+#pragma unroll
+        for (int p = 0; p < LB; ++p) {
+            const int idx = tid + p * NT;
+            const int kk = BNK ? idx % BK : idx / BN;
+            const int nn = BNK ? idx / BK : idx % BN;
+            const int64_t gn = n0 + nn, gk = k0 + kk;
+            TI v = (TI)0;
+            if (gn < g.N && gk < kend) v = BNK ? Bp[gn * g.ldb + gk] : Bp[gk * g.ldb + gn];
+            rb[p] = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < LA; ++p) {
+            const int idx = tid + p * NT;
+            const int kk = AKM ? idx / BM : idx % BK;
+            const int mm = AKM ? idx % BM : idx / BK;
+            sA[buf][kk][mm] = ra[p];
+        }
+#pragma unroll
+        for (int p = 0; p < LB; ++p) {
+            const int idx = tid + p * NT;
+            const int kk = BNK ? idx % BK : idx / BN;
+            const int nn = BNK ? idx / BK : idx % BN;
+            sB[buf][kk][nn] = rb[p];
+        }
+    };
+
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = acc_t{0, 0, 0, 0};
+
+    const int64_t nchunk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+    if (nchunk > 0) {
+        load(kbeg);
+        store(0);
+        __syncthreads();
+        const int lr = lane >> 4, lc = lane & 15;
+        for (int64_t c = 0; c < nchunk; ++c) {
+            const int cur = (int)(c & 1);
+            if (c + 1 < nchunk) load(kbeg + (c + 1) * BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                TI a[FM], b[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) a[i] = sA[cur][kk + lr][wm * WTM + i * 16 + lc];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) b[j] = sB[cur][kk + lr][wn * WTN + j * 16 + lc];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = Mfma<TI>::op(a[i], b[j], acc[i][j]);
+            }
+            if (c + 1 < nchunk) store(cur ^ 1);
+            __syncthreads();
+        }
+    }
+
+    // epilogue
+    const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm * WTM + i * 16 + Mfma<TI>::row(lr, r);
+                const int64_t col = n0 + wn * WTN + j * 16 + lc;
+                if (row >= g.M || col >= g.N) continue;
+                if (LOWER && col > row) continue;
+                const double v = (double)acc[i][j][r];
+                if (EPI == EPI_SUB) {
+                    g.C[row * g.ldc + col] -= v;
+                } else if (EPI == EPI_STORE) {
+                    g.C[row * g.ldc + col] = v;
+                } else if (EPI == EPI_PARTIAL) {
+                    g.C[(int64_t)blockIdx.z * g.pstride + row * g.ldc + col] = v;
+                } else if (EPI == EPI_SYMLOW) {
+                    if (row >= col) {
+                        g.C[row * g.ldc + col] = v;
+                        g.C[col * g.ldc + row] = v;
+                    }
+                } else {  // EPI_PHI
+                    g.C[row * g.ldc + col] = v;
+                    g.C2[row * g.ldc2 + col] = row > col ? v : (row == col ? 0.5 * v : 0.0);
+                }
+            }
+}
+
+template <typename TI, int BM, int BN, int BK, bool AKM, bool BNK, int EPI, bool LOWER>
+hipError_t launch(hipStream_t s, const GemmArgs& g, int splits)
+{
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    int64_t tiles;
+    if (LOWER) {
+        const int64_t t = (g.M + BM - 1) / BM;
+        tiles = t * (t + 1) / 2;
+    } else {
+        tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    }
+    dim3 grid((unsigned)tiles, 1, (unsigned)(splits < 1 ? 1 : splits));
+    hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, BK, AKM, BNK, EPI, LOWER>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define GPC_GEMM_CASE(TI, CFG, BM, BN, BK, AKM, BNK, EPI, LOWER)                                 \
+    if (cfg == CFG && a_km == AKM && b_nk == BNK && epi == EPI && lower_tiles == LOWER)           \
+        return launch<TI, BM, BN, BK, AKM, BNK, EPI, LOWER>(s, g, splits);
+
+hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, bool lower_tiles,
+                    const GemmArgs& g, int splits)
+{
+    // trailing SYRK (lower tiles), panel solve, adjoint panel solve and updates
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_SUB, true)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_STORE, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, false, EPI_STORE, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, false, EPI_SUB, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, false, EPI_PARTIAL, false)
+    GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_PARTIAL, false)
+    // diagonal-block reverse step
+    GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_SYMLOW, false)
+    GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, false, false, EPI_STORE, false)
+    GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_PHI, false)
+    return hipErrorInvalidValue;
+}
+
+hipError_t gemm_f32in(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, bool lower_tiles,
+                      const GemmArgs& g, int splits)
+{
+    GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, true, EPI_SUB, true)
+    GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, false, EPI_SUB, false)
+    GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, true, false, EPI_PARTIAL, false)
+    GPC_GEMM_CASE(float, TILE_64, 64, 64, 32, true, false, EPI_PARTIAL, false)
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gpc

@@ -1,0 +1,79 @@
+// Internal declarations shared by the HIP translation units of libgpchol.
+// Row-major storage throughout: element (i, j) of X is X[i * ld + j].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpc {
+
+// Largest diagonal block handled inside one workgroup's LDS.
+constexpr int kDiagMax = 128;
+
+// ---- GEMM on MFMA ---------------------------------------------------------
+// acc[m][n] = sum_{k in [k0,k1)} Aop[m][k] * Bop[k][n], then an epilogue.
+//   A layout  MK: Aop[m][k] = A[m*lda + k]      KM: Aop[m][k] = A[k*lda + m]
+//   B layout  KN: Bop[k][n] = B[k*ldb + n]      NK: Bop[k][n] = B[n*ldb + k]
+// For layout KM the first `head_k` values of k may come from a separate
+// matrix `Ahead` (row k of Ahead, leading dimension ldah); k >= head_k then
+// reads row (k - head_k) of A.
+enum Epi : int {
+    EPI_SUB = 0,      // C[m][n] -= acc
+    EPI_STORE = 1,    // C[m][n]  = acc   (C may alias A when one tile spans all N)
+    EPI_PARTIAL = 2,  // C[z*pstride + m*ldc + n] = acc   (split-K slice z)
+    EPI_SYMLOW = 3,   // for m >= n: C[m][n] = C[n][m] = acc   (symmetric from lower)
+    EPI_PHI = 4       // C[m][n] = acc (full);  C2[m][n] = m>n ? acc : m==n ? acc/2 : 0
+};
+
+struct GemmArgs {
+    int64_t M, N, K;
+    const void* A; int64_t lda;
+    const void* B; int64_t ldb;
+    double* C; int64_t ldc;
+    double* C2; int64_t ldc2;
+    const void* Ahead; int64_t ldah; int64_t head_k;
+    int64_t kchunk;     // split-K chunk (multiple of the kernel's BK); splits = gridDim.z
+    int64_t pstride;    // EPI_PARTIAL slice stride (elements)
+    int32_t a_lower;    // nonzero: A is lower-triangular as stored; its strict upper is never read
+};
+
+enum TileCfg : int { TILE_128 = 0, TILE_64 = 1 };
+
+// Launchers (hipError_t from the launch).  `lower_tiles`: M == N and only tiles
+// on or below the diagonal are computed, and only elements with m >= n written.
+hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi,
+                    bool lower_tiles, const GemmArgs& g, int splits);
+hipError_t gemm_f32in(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi,
+                      bool lower_tiles, const GemmArgs& g, int splits);
+
+// ---- diagonal blocks (single workgroup each) ------------------------------
+// Factor the kb x kb diagonal block at A (in place, upper zeroed), write its
+// inverse (lower, kb x kb, leading dimension ldi, upper zeroed) to Linv, and
+// record the first failing pivot as info = col0 + j + 1 if info is still 0.
+hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Linv,
+                      int64_t ldi, int32_t* info, int64_t col0);
+// Inverses of the diagonal blocks of L: block q covers rows/cols [q*b, min(n,(q+1)*b)),
+// its inverse goes to Dinv + q*b*b (leading dimension b, upper zeroed).
+hipError_t trtri_diag_batched(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl,
+                              double* Dinv);
+
+// ---- elementwise helpers ---------------------------------------------------
+hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v);
+hipError_t zero_strict_upper(hipStream_t s, int64_t n, double* A, int64_t lda);
+// C[m][n] -= sum_{z<S} P[z*pstride + m*N + n], z increasing.
+hipError_t reduce_sub(hipStream_t s, int64_t M, int64_t N, const double* P, int S,
+                      int64_t pstride, double* C, int64_t ldc);
+// W[m][n] = m >= n ? D[m][n] - sum_z P[z][m][n] : 0   (b x b, W leading dim b)
+hipError_t reduce_tril(hipStream_t s, int b, const double* D, int64_t ldd, const double* P,
+                       int S, int64_t pstride, double* W);
+
+// ---- solves and log-determinant --------------------------------------------
+// B <- L^-1 B (trans 0) or L^-T B (trans 1) by block steps with the diagonal
+// block inverses Dinv (as from trtri_diag_batched, block b).  Y: workspace of
+// 8 * n doubles.
+hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L,
+                        int64_t ldl, const double* Dinv, int b, double* B, int64_t ldb, double* Y);
+// *out = 2 * sum_i log L_ii (fixed summation order).
+hipError_t logdet(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* out);
+
+}  // namespace gpc

@@ -1,0 +1,211 @@
+"""ctypes binding of libgpchol (include/gpchol.h): argument marshalling only.
+
+Tensors are torch float64 CUDA (HIP) tensors, 2-D, row-major with unit column
+stride (``t.stride(1) == 1``); the row stride is passed as the leading
+dimension, so sub-matrix views work.  Every call enqueues on torch's current
+stream of the tensor's device and returns without waiting.  All arithmetic runs
+in the library's HIP kernels; there is no fallback: if ``libgpchol.so`` is
+missing or the device is not gfx950, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpchol.so")
+
+GPC_OK, GPC_ERR_ARG, GPC_ERR_NO_DEVICE, GPC_ERR_ARCH, GPC_ERR_HIP, GPC_ERR_REFINE, GPC_ERR_ALLOC = range(7)
+GPC_FP64, GPC_MIXED = 0, 1
+GPC_NOTRANS, GPC_TRANS = 0, 1
+
+# Every symbol the header declares, in declaration order.
+EXPORTS = (
+    "gpc_create", "gpc_destroy", "gpc_set_stream", "gpc_set_options", "gpc_get_options",
+    "gpc_factor", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
+    "gpc_trace_enable", "gpc_trace_reset", "gpc_trace_read",
+    "gpc_status_string", "gpc_last_error",
+)
+
+# Kernel classes of the launch trace (gpc_kernel_class).
+KERNEL_CLASSES = ("diag_factor", "panel_solve", "trailing_update", "diag_inverse", "adj_panel_solve",
+                  "adj_left_update", "adj_diag_product", "adj_diag_block", "adj_row_update", "reduce")
+
+
+class GpcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class gpc_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("lookahead", ctypes.c_int32), ("refine_maxit", ctypes.c_int32),
+                ("refine_tol", ctypes.c_double)]
+
+
+_i64, _i32, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgpchol.so and declare the C signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1907_01063_amd.build`")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "gpc_create": [ctypes.POINTER(_vp), _vp],
+        "gpc_destroy": [_vp],
+        "gpc_set_stream": [_vp, _vp],
+        "gpc_set_options": [_vp, ctypes.POINTER(gpc_options)],
+        "gpc_get_options": [_vp, ctypes.POINTER(gpc_options)],
+        "gpc_factor": [_vp, _i64, _vp, _i64, _vp],
+        "gpc_adjoint": [_vp, _i64, _vp, _i64, _vp, _i64],
+        "gpc_trsm": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64],
+        "gpc_logdet": [_vp, _i64, _vp, _i64, _vp],
+        "gpc_trace_enable": [_vp, _i32],
+        "gpc_trace_reset": [_vp],
+        "gpc_trace_read": [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.gpc_status_string.argtypes = [ctypes.c_int]
+    lib.gpc_status_string.restype = ctypes.c_char_p
+    lib.gpc_last_error.argtypes = [_vp]
+    lib.gpc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+def _mat(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.dim() != 2 or not t.is_cuda:
+        raise TypeError(f"{name}: expected a 2-D float64 GPU tensor")
+    if t.shape[0] != 0 and t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name}: needs unit column stride (row-major)")
+    return t.stride(0) if t.shape[0] > 1 else max(1, t.shape[1])
+
+
+class Handle:
+    """One library handle per (device, host thread).  Calls follow torch's
+    current stream at call time."""
+
+    def __init__(self, device=None, precision: int = GPC_FP64, block: int = 0):
+        self.lib = load_library()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            st = self.lib.gpc_create(ctypes.byref(h), _vp(torch.cuda.current_stream().cuda_stream))
+        if st != GPC_OK:
+            raise GpcError(st, f"gpc_create: {self.lib.gpc_status_string(st).decode()}")
+        self.h = h
+        if precision != GPC_FP64 or block != 0:
+            self.set_options(precision=precision, block=block)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.gpc_destroy(h)
+            self.h = None
+
+    def _check(self, st: int, what: str):
+        if st != GPC_OK:
+            msg = self.lib.gpc_last_error(self.h).decode() if self.h else ""
+            raise GpcError(st, f"{what}: {self.lib.gpc_status_string(st).decode()} {msg}".strip())
+
+    def _sync_stream(self):
+        self.lib.gpc_set_stream(self.h, _vp(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def options(self) -> gpc_options:
+        o = gpc_options()
+        self._check(self.lib.gpc_get_options(self.h, ctypes.byref(o)), "gpc_get_options")
+        return o
+
+    def set_options(self, **kw):
+        o = self.options()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        self._check(self.lib.gpc_set_options(self.h, ctypes.byref(o)), "gpc_set_options")
+
+    # --- entry points (same names as the C ABI, without the prefix) ---
+    def factor(self, A: torch.Tensor, info: torch.Tensor | None = None) -> torch.Tensor:
+        """In place: tril(A) <- L, strict upper <- 0.  Returns the device int32 info."""
+        lda = _mat(A, "A")
+        n = A.shape[0]
+        if A.shape[1] != n:
+            raise ValueError("A must be square")
+        if info is None:
+            info = torch.empty((), dtype=torch.int32, device=A.device)
+        self._sync_stream()
+        self._check(self.lib.gpc_factor(self.h, n, _ptr(A), lda, _ptr(info)), "gpc_factor")
+        return info
+
+    def adjoint(self, L: torch.Tensor, Lbar: torch.Tensor) -> torch.Tensor:
+        """In place: tril(Lbar) <- Abar, strict upper <- 0.  Returns Lbar."""
+        ldl, ldb = _mat(L, "L"), _mat(Lbar, "Lbar")
+        n = L.shape[0]
+        if L.shape != (n, n) or Lbar.shape != (n, n):
+            raise ValueError("L and Lbar must be n x n")
+        self._sync_stream()
+        self._check(self.lib.gpc_adjoint(self.h, n, _ptr(L), ldl, _ptr(Lbar), ldb), "gpc_adjoint")
+        return Lbar
+
+    def trsm(self, L: torch.Tensor, B: torch.Tensor, trans: bool = False) -> torch.Tensor:
+        """In place: B <- L^-1 B (or L^-T B).  B is n x nrhs (a 1-D B is one column)."""
+        ldl = _mat(L, "L")
+        B2 = B.unsqueeze(1) if B.dim() == 1 else B
+        ldb = _mat(B2, "B")
+        n = L.shape[0]
+        if B2.shape[0] != n:
+            raise ValueError("B must have n rows")
+        self._sync_stream()
+        self._check(self.lib.gpc_trsm(self.h, GPC_TRANS if trans else GPC_NOTRANS, n, B2.shape[1],
+                                      _ptr(L), ldl, _ptr(B2), ldb), "gpc_trsm")
+        return B
+
+    def trace_enable(self, on: bool = True):
+        self._check(self.lib.gpc_trace_enable(self.h, 1 if on else 0), "gpc_trace_enable")
+
+    def trace_reset(self):
+        self._sync_stream()
+        self._check(self.lib.gpc_trace_reset(self.h), "gpc_trace_reset")
+
+    def trace_read(self) -> dict:
+        """{class name: (launches, ms, flops, bytes)} for every kernel class."""
+        out = {}
+        for k, name in enumerate(KERNEL_CLASSES):
+            n, ms, fl, by = _i64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            self._check(self.lib.gpc_trace_read(self.h, k, ctypes.byref(n), ctypes.byref(ms),
+                                                ctypes.byref(fl), ctypes.byref(by)), "gpc_trace_read")
+            out[name] = (n.value, ms.value, fl.value, by.value)
+        return out
+
+    def logdet(self, L: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        ldl = _mat(L, "L")
+        if out is None:
+            out = torch.empty((), dtype=torch.float64, device=L.device)
+        self._sync_stream()
+        self._check(self.lib.gpc_logdet(self.h, L.shape[0], _ptr(L), ldl, _ptr(out)), "gpc_logdet")
+        return out
+
+
+_handles: dict = {}
+
+
+def default_handle(device=None) -> Handle:
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    if dev not in _handles:
+        _handles[dev] = Handle(device=dev)
+    return _handles[dev]

@@ -1,0 +1,60 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+public header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1907_01063_amd import gpchol
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpchol.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpc_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_expected_entry_points():
+    syms = declared_symbols()
+    for s in ("gpc_create", "gpc_factor", "gpc_adjoint", "gpc_trsm", "gpc_logdet"):
+        assert s in syms
+    assert sorted(gpchol.EXPORTS) == syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gpchol.load_library()
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+
+
+def test_null_handle_and_bad_arguments_rejected():
+    lib = gpchol.load_library()
+    E = gpchol.GPC_ERR_ARG
+    assert lib.gpc_factor(None, 4, None, 4, None) == E
+    assert lib.gpc_adjoint(None, 4, None, 4, None, 4) == E
+    assert lib.gpc_trsm(None, 0, 4, 1, None, 4, None, 1) == E
+    assert lib.gpc_logdet(None, 4, None, 4, None) == E
+    assert lib.gpc_destroy(None) == E
+    assert lib.gpc_create(None, None) == E
+    assert lib.gpc_set_options(None, None) == E
+
+
+def test_status_strings():
+    lib = gpchol.load_library()
+    for code in range(7):
+        assert lib.gpc_status_string(code)
+    assert lib.gpc_status_string(99) == b"unknown status"
+
+
+def test_create_without_device_reports_no_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    lib = gpchol.load_library()
+    h = ctypes.c_void_p()
+    assert lib.gpc_create(ctypes.byref(h), None) == gpchol.GPC_ERR_NO_DEVICE
+    assert not h.value
