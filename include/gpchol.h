@@ -108,6 +108,46 @@ gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs,
  * (independent of launch shape).  out_dev: one device double. */
 gpc_status gpc_logdet(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* out_dev);
 
+/* Iterative refinement (mixed precision): solve K x = y in FP64 with a
+ * factor L of K that may carry FP32 rounding in its trailing updates
+ * (GPC_MIXED).  x_0 = 0; then repeat d = L^-T L^-1 r, x += d, r = y - K x
+ * (residual in FP64 from the lower triangle of K) until the normwise
+ * backward error eta_inf = |r|_inf / (|K|_inf |x|_inf + |y|_inf) is at most
+ * the handle's refine_tol, or refine_maxit iterations have run.  y, x: device
+ * n-vectors; iters_dev (int32) and eta_dev (double): device scalars.  Waits
+ * for the stream once per iteration to read eta.  Returns GPC_ERR_REFINE if
+ * the tolerance was not reached (x, iters and eta are still written). */
+gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t ldk, const double* L,
+                             int64_t ldl, const double* y, double* x, int32_t* iters_dev, double* eta_dev);
+
+/* GP covariance (squared-exponential with one lengthscale per input
+ * dimension, the kernel of the GP regression example, section 4.2):
+ * K_ij = s2 exp(-1/2 sum_q (x_iq - x_jq)^2 / l_q^2) + sn2 [i == j], written to
+ * the lower triangle of K (strict upper := 0).  X: n x d row-major device
+ * array, 1 <= d <= 16.  theta: d+2 device doubles (s2, l_1..l_d, sn2). */
+gpc_status gpc_gp_kgen_se(gpc_handle* h, int64_t n, int32_t d, const double* X, const double* theta,
+                          double* K, int64_t ldk);
+
+/* GP log-density pieces from the factor L of K (section 1: the density needs
+ * the inverse and the determinant of the covariance, through its factor):
+ * z = L^-1 y, alpha = L^-T z (device n-vectors), logdet = 2 sum log L_ii and
+ * f = -1/2 z^T z - 1/2 logdet (device scalars; the constant -n/2 log 2 pi is
+ * left out).  All sums in a fixed order. */
+gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, const double* y, double* z,
+                        double* alpha, double* logdet_dev, double* f_dev);
+
+/* Adjoint of the factor for that density: Lbar = tril(alpha z^T) - diag(1/L_ii)
+ * (lower triangle; strict upper := 0). */
+gpc_status gpc_gp_lbar(gpc_handle* h, int64_t n, const double* L, int64_t ldl, const double* alpha,
+                       const double* z, double* Lbar, int64_t ldlb);
+
+/* Chain rule from Abar (the adjoint of the lower-triangle entries of K, as
+ * returned by gpc_adjoint) to theta:
+ * grad_q = scale * sum_{i>=j} Abar_ij dK_ij / dtheta_q  (d+2 device doubles;
+ * scale: device double or NULL for 1).  Fixed summation order. */
+gpc_status gpc_gp_hypergrad_se(gpc_handle* h, int64_t n, int32_t d, const double* X, const double* theta,
+                               const double* Abar, int64_t ldab, const double* scale_dev, double* grad_dev);
+
 /* Kernel classes reported by the launch trace below. */
 typedef enum {
     GPC_K_DIAG_FACTOR = 0,      /* diagonal-block factor + inverse (one workgroup) */

@@ -261,9 +261,14 @@ gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t*
     GPC_HIP(h, fill_i32(s, info, 0));
     if (n == 0) return GPC_OK;
     const int b = block_of(h);
-    gpc_status st = ensure_ws(h, sizeof(double) * (size_t)b * b);
+    const bool mixed = h->opt.precision == GPC_MIXED;
+    // FP64 inverse of the diagonal block; FP32 copy of the panel (mixed)
+    const size_t n_linv = (size_t)b * b;
+    const size_t n_pf = mixed ? (size_t)n * b : 0;
+    gpc_status st = ensure_ws(h, sizeof(double) * n_linv + sizeof(float) * n_pf);
     if (st != GPC_OK) return st;
     double* Linv = (double*)h->ws;
+    float* Pf = (float*)(Linv + n_linv);
     for (int64_t k = 0; k < n; k += b) {
         const int kb = (int)std::min<int64_t>(b, n - k);
         const double dkb = (double)kb;
@@ -279,13 +284,22 @@ gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t*
         {
             Traced t(h, GPC_K_PANEL_SOLVE, dm * dkb * dkb, 8.0 * (2.0 * dm * dkb + dkb * dkb));
             GemmArgs pg = gemm_args(m, kb, kb, A21, lda, Linv, b, A21, lda);
+            if (mixed) {
+                pg.Cf = Pf;
+                pg.ldcf = b;
+            }
             GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_STORE, false, pg, 1));
         }
         {
             Traced t(h, GPC_K_TRAILING_UPDATE, dm * (dm + 1.0) * dkb,
-                     8.0 * (dm * dkb + dm * (dm + 1.0)));
-            GemmArgs sg = gemm_args(m, m, kb, A21, lda, A21, lda, A22, lda);
-            GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_SUB, true, sg, 1));
+                     (mixed ? 4.0 : 8.0) * dm * dkb + 8.0 * dm * (dm + 1.0));
+            if (mixed) {
+                GemmArgs sg = gemm_args(m, m, kb, Pf, b, Pf, b, A22, lda);
+                GPC_HIP(h, gemm_f32in(s, TILE_128, false, true, EPI_SUB, true, sg, 1));
+            } else {
+                GemmArgs sg = gemm_args(m, m, kb, A21, lda, A21, lda, A22, lda);
+                GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_SUB, true, sg, 1));
+            }
         }
     }
     GPC_HIP(h, zero_strict_upper(s, n, A, lda));
@@ -322,9 +336,15 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         splitk_plan(((bq + 127) / 128) * ((j + 127) / 128), bq + (n - k), kMaxSr, &sr, &ch);
         pr_elems = std::max<int64_t>(pr_elems, (int64_t)sr * bq * j);
     }
+    const bool mixed = h->opt.precision == GPC_MIXED;
     const size_t bb = (size_t)b * b;
     const size_t n_dinv = (size_t)nblk * bb, n_pd = (size_t)kMaxSd * bb;
-    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + n_pd + 4 * bb + (size_t)pr_elems));
+    const size_t n_dbl = n_dinv + n_pd + 4 * bb + (size_t)pr_elems;
+    // mixed: FP32 copies of the strict lower triangle of L, of the current
+    // Cbar panel and of M (the FP32 operands of the two trailing products)
+    const int64_t ldf = n;
+    const size_t n_flt = mixed ? (size_t)n * n + (size_t)n * b + bb : 0;
+    gpc_status st = ensure_ws(h, sizeof(double) * n_dbl + sizeof(float) * n_flt);
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
     double* Pd = Dinv + n_dinv;
@@ -333,6 +353,10 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     double* Tw = Sw + bb;
     double* Mw = Tw + bb;
     double* Pr = Mw + bb;
+    float* Lf = (float*)(Pr + pr_elems);
+    float* Cf = Lf + (size_t)n * n;
+    float* Mf = Cf + (size_t)n * b;
+    if (mixed) GPC_HIP(h, convert_lower_f32(s, n, L, ldl, Lf, ldf));
 
     {
         const double db = (double)b;
@@ -352,13 +376,22 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
             {
                 Traced t(h, GPC_K_ADJ_PANEL_SOLVE, dnr * dbq * dbq, 8.0 * (2.0 * dnr * dbq + dbq * dbq));
                 GemmArgs g5 = gemm_args(nr, bq, bq, Cbar, ldlb, Dq_inv, b, Cbar, ldlb);
+                if (mixed) {
+                    g5.Cf = Cf;
+                    g5.ldcf = b;
+                }
                 GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g5, 1));
             }
             if (j > 0) {
                 Traced t(h, GPC_K_ADJ_LEFT_UPDATE, 2.0 * dnr * dj * dbq,
-                         8.0 * (2.0 * dnr * dj + dnr * dbq + dbq * dj));
-                GemmArgs g6 = gemm_args(nr, j, bq, Cbar, ldlb, L + j * ldl, ldl, Lbar + k * ldlb, ldlb);
-                GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_SUB, false, g6, 1));
+                         16.0 * dnr * dj + (mixed ? 4.0 : 8.0) * (dnr * dbq + dbq * dj));
+                if (mixed) {
+                    GemmArgs g6 = gemm_args(nr, j, bq, Cf, b, Lf + j * ldf, ldf, Lbar + k * ldlb, ldlb);
+                    GPC_HIP(h, gemm_f32in(s, TILE_128, false, false, EPI_SUB, false, g6, 1));
+                } else {
+                    GemmArgs g6 = gemm_args(nr, j, bq, Cbar, ldlb, L + j * ldl, ldl, Lbar + k * ldlb, ldlb);
+                    GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_SUB, false, g6, 1));
+                }
             }
             int64_t ch;
             splitk_plan(((bq + 63) / 64) * ((bq + 63) / 64), nr, kMaxSd, &sd, &ch);
@@ -379,6 +412,10 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
             GemmArgs gm = gemm_args(bq, bq, bq, Dq_inv, b, Tw, bq, Mw, bq);
             gm.C2 = Dbar;
             gm.ldc2 = ldlb;
+            if (mixed) {
+                gm.Cf = Mf;
+                gm.ldcf = bq;
+            }
             GPC_HIP(h, gemm_f64(s, TILE_64, true, false, EPI_PHI, false, gm, 1));
         }
         if (j > 0) {
@@ -387,14 +424,24 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
             splitk_plan(((bq + 127) / 128) * ((j + 127) / 128), K, kMaxSr, &sr, &ch);
             {
                 Traced t(h, GPC_K_ADJ_ROW_UPDATE, 2.0 * dbq * dj * (double)K,
-                         8.0 * ((double)K * (dbq + dj) + sr * dbq * dj));
-                GemmArgs gr = gemm_args(bq, j, K, Cbar, ldlb, L + j * ldl, ldl, Pr, j);
-                gr.Ahead = Mw;
-                gr.ldah = bq;
-                gr.head_k = bq;
-                gr.kchunk = ch;
-                gr.pstride = bq * j;
-                GPC_HIP(h, gemm_f64(s, TILE_128, true, false, EPI_PARTIAL, false, gr, sr));
+                         (mixed ? 4.0 : 8.0) * (double)K * (dbq + dj) + 8.0 * sr * dbq * dj);
+                if (mixed) {
+                    GemmArgs gr = gemm_args(bq, j, K, Cf, b, Lf + j * ldf, ldf, Pr, j);
+                    gr.Ahead = Mf;
+                    gr.ldah = bq;
+                    gr.head_k = bq;
+                    gr.kchunk = ch;
+                    gr.pstride = bq * j;
+                    GPC_HIP(h, gemm_f32in(s, TILE_128, true, false, EPI_PARTIAL, false, gr, sr));
+                } else {
+                    GemmArgs gr = gemm_args(bq, j, K, Cbar, ldlb, L + j * ldl, ldl, Pr, j);
+                    gr.Ahead = Mw;
+                    gr.ldah = bq;
+                    gr.head_k = bq;
+                    gr.kchunk = ch;
+                    gr.pstride = bq * j;
+                    GPC_HIP(h, gemm_f64(s, TILE_128, true, false, EPI_PARTIAL, false, gr, sr));
+                }
             }
             Traced t(h, GPC_K_REDUCE, dbq * dj * sr, 8.0 * (sr + 2.0) * dbq * dj);
             GPC_HIP(h, reduce_sub(s, bq, j, Pr, sr, bq * j, Lbar + j * ldlb, ldlb));
@@ -430,6 +477,113 @@ gpc_status gpc_logdet(gpc_handle* h, int64_t n, const double* L, int64_t ldl, do
     if (!h || n < 0 || !ld_ok(n, ldl) || !out || (n > 0 && !L)) return GPC_ERR_ARG;
     GPC_HIP(h, logdet(h->stream, n, L, ldl, out));
     return GPC_OK;
+}
+
+// --------------------------------------------------------------- GP -------
+gpc_status gpc_gp_kgen_se(gpc_handle* h, int64_t n, int32_t d, const double* X, const double* theta,
+                          double* K, int64_t ldk)
+{
+    if (!h || n < 0 || d < 1 || d > kMaxGpDim || !ld_ok(n, ldk) || (n > 0 && (!X || !theta || !K)))
+        return GPC_ERR_ARG;
+    GPC_HIP(h, gp_kgen_se(h->stream, n, d, X, theta, K, ldk));
+    return GPC_OK;
+}
+
+gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, const double* y, double* z,
+                        double* alpha, double* logdet_out, double* f_out)
+{
+    if (!h || n < 0 || !ld_ok(n, ldl) || !logdet_out || !f_out || (n > 0 && (!L || !y || !z || !alpha)))
+        return GPC_ERR_ARG;
+    hipStream_t s = h->stream;
+    if (n > 0) {
+        const int b = block_of(h);
+        const int64_t nblk = (n + b - 1) / b;
+        const size_t n_dinv = (size_t)nblk * b * b;
+        gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + 8 * (size_t)n));
+        if (st != GPC_OK) return st;
+        double* Dinv = (double*)h->ws;
+        double* Y = Dinv + n_dinv;
+        GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+        GPC_HIP(h, vec_copy(s, n, y, z));
+        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, b, z, 1, Y));
+        GPC_HIP(h, vec_copy(s, n, z, alpha));
+        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, b, alpha, 1, Y));
+    }
+    GPC_HIP(h, logdet(s, n, L, ldl, logdet_out));
+    GPC_HIP(h, gp_value(s, n, z, logdet_out, f_out));
+    return GPC_OK;
+}
+
+gpc_status gpc_gp_lbar(gpc_handle* h, int64_t n, const double* L, int64_t ldl, const double* alpha,
+                       const double* z, double* Lbar, int64_t ldlb)
+{
+    if (!h || n < 0 || !ld_ok(n, ldl) || !ld_ok(n, ldlb) || (n > 0 && (!L || !alpha || !z || !Lbar)))
+        return GPC_ERR_ARG;
+    GPC_HIP(h, gp_lbar(h->stream, n, L, ldl, alpha, z, Lbar, ldlb));
+    return GPC_OK;
+}
+
+gpc_status gpc_gp_hypergrad_se(gpc_handle* h, int64_t n, int32_t d, const double* X, const double* theta,
+                               const double* Abar, int64_t ldab, const double* scale, double* grad)
+{
+    if (!h || n < 0 || d < 1 || d > kMaxGpDim || !ld_ok(n, ldab) || !theta || !grad ||
+        (n > 0 && (!X || !Abar)))
+        return GPC_ERR_ARG;
+    gpc_status st = ensure_ws(h, sizeof(double) * (size_t)gp_hypergrad_parts(n, d));
+    if (st != GPC_OK) return st;
+    GPC_HIP(h, gp_hypergrad_se(h->stream, n, d, X, theta, Abar, ldab, scale, grad, (double*)h->ws));
+    return GPC_OK;
+}
+
+// ------------------------------------------------------------ refinement ---
+// Solve K x = y with a factor L of (an approximation of) K: x_0 = 0, then
+// repeat  d = L^-T L^-1 r,  x += d,  r = y - K x  (FP64, K from its lower
+// triangle),  eta = |r|_inf / (|K|_inf |x|_inf + |y|_inf)  until eta <= tol.
+gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t ldk, const double* L,
+                             int64_t ldl, const double* y, double* x, int32_t* iters, double* eta)
+{
+    if (!h || n < 0 || !ld_ok(n, ldk) || !ld_ok(n, ldl) || !iters || !eta ||
+        (n > 0 && (!K || !L || !y || !x)))
+        return GPC_ERR_ARG;
+    hipStream_t s = h->stream;
+    if (n == 0) {
+        GPC_HIP(h, fill_i32(s, iters, 0));
+        GPC_HIP(h, vec_zero(s, 1, eta));
+        return GPC_OK;
+    }
+    const int b = block_of(h);
+    const int64_t nblk = (n + b - 1) / b;
+    const size_t n_dinv = (size_t)nblk * b * b;
+    const size_t n_part = (size_t)symv_parts(n);
+    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + 8 * (size_t)n + n_part + 3 * (size_t)n));
+    if (st != GPC_OK) return st;
+    double* Dinv = (double*)h->ws;
+    double* Y = Dinv + n_dinv;
+    double* part = Y + 8 * (size_t)n;
+    double* rowabs = part + n_part;
+    double* r = rowabs + n;
+    double* d = r + n;
+    GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+    GPC_HIP(h, symv_lower(s, n, K, ldk, nullptr, 1, nullptr, 1.0, rowabs, part));
+    GPC_HIP(h, vec_zero(s, n, x));
+    GPC_HIP(h, vec_copy(s, n, y, r));
+    const int maxit = std::max(1, h->opt.refine_maxit);
+    double eta_h = 1.0;
+    int it = 0;
+    while (it < maxit) {
+        ++it;
+        GPC_HIP(h, vec_copy(s, n, r, d));
+        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, b, d, 1, Y));
+        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, b, d, 1, Y));
+        GPC_HIP(h, vec_axpy(s, n, d, x));
+        GPC_HIP(h, symv_lower(s, n, K, ldk, x, 0, y, -1.0, r, part));
+        GPC_HIP(h, refine_eta(s, n, r, x, y, rowabs, eta));
+        GPC_HIP(h, hipMemcpyAsync(&eta_h, eta, sizeof(double), hipMemcpyDeviceToHost, s));
+        GPC_HIP(h, hipStreamSynchronize(s));
+        if (eta_h <= h->opt.refine_tol) break;
+    }
+    GPC_HIP(h, fill_i32(s, iters, it));
+    return eta_h <= h->opt.refine_tol ? GPC_OK : GPC_ERR_REFINE;
 }
 
 }  // extern "C"

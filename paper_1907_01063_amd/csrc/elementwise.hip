@@ -19,6 +19,13 @@ __global__ void zero_upper_kernel(int64_t n, double* A, int64_t lda)
     if (r < n && c < n && c > r) A[r * lda + c] = 0.0;
 }
 
+__global__ void convert_lower_kernel(int64_t n, const double* L, int64_t ldl, float* Lf, int64_t ldf)
+{
+    const int64_t r = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    if (r < n && c < r) Lf[r * ldf + c] = (float)L[r * ldl + c];
+}
+
 __global__ void reduce_sub_kernel(int64_t M, int64_t N, const double* P, int S, int64_t pstride,
                                   double* C, int64_t ldc)
 {
@@ -58,6 +65,14 @@ hipError_t zero_strict_upper(hipStream_t s, int64_t n, double* A, int64_t lda)
     if (n <= 1) return hipSuccess;
     dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 3) / 4));
     hipLaunchKernelGGL(zero_upper_kernel, grid, dim3(256), 0, s, n, A, lda);
+    return hipGetLastError();
+}
+
+hipError_t convert_lower_f32(hipStream_t s, int64_t n, const double* L, int64_t ldl, float* Lf, int64_t ldf)
+{
+    if (n <= 1) return hipSuccess;
+    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 3) / 4));
+    hipLaunchKernelGGL(convert_lower_kernel, grid, dim3(256), 0, s, n, L, ldl, Lf, ldf);
     return hipGetLastError();
 }
 

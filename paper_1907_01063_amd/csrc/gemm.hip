@@ -4,9 +4,9 @@
 // L21 = A21 L11^-T and the trailing update A22 - L21 L21^T of section 3.3.1)
 // and of its blocked reverse sweep (the products of section 3.3.2).
 //
-// A workgroup of 4 waves (2 x 2) owns a BM x BN output tile; each wave owns a
-// (BM/2) x (BN/2) sub-tile made of 16x16 MFMA blocks held in accumulator
-// registers.  The k dimension is walked in chunks of BK: the next chunk is
+// A workgroup owns a BM x BN output tile: 8 waves (2 x 4) for 128 x 128
+// tiles, 4 waves (2 x 2) for 64 x 64; each wave owns a sub-tile made of 16x16
+// MFMA blocks held in accumulator registers.  The k dimension is walked in chunks of BK: the next chunk is
 // loaded from global memory into registers while the current chunk is consumed
 // from LDS (two LDS buffers, one barrier per chunk).  Operands are staged in
 // LDS k-major (sA[k][m], sB[k][n]) so that each MFMA operand fetch reads 16
@@ -41,14 +41,17 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int lr, int r) { return 4 * lr + r; }
 };
 
-template <typename TI, int BM, int BN, int BK, bool AKM, bool BNK, int EPI, bool LOWER>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
+template <typename TI, int BM, int BN, int BK, int WM, int WN, bool AKM, bool BNK, int EPI, bool LOWER>
+__global__ void __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(WM * WN == 8 ? 4 : 2))) gemm_kernel(GemmArgs g)
 {
-    constexpr int NT = 256;
-    constexpr int WTM = BM / 2, WTN = BN / 2;   // wave sub-tile
+    constexpr int NT = WM * WN * 64;
+    constexpr int WTM = BM / WM, WTN = BN / WN;  // wave sub-tile
     constexpr int FM = WTM / 16, FN = WTN / 16;  // MFMA blocks per wave
     constexpr int PAD = sizeof(TI) == 8 ? 2 : 4;
     constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+    // per-load step of the strided index: rows (MK/NK) or k rows (KM/KN)
+    constexpr int ASTEP = AKM ? NT / BM : NT / BK;
+    constexpr int BSTEP = BNK ? NT / BK : NT / BN;
     static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile/thread mismatch");
     typedef typename Mfma<TI>::acc_t acc_t;
 
@@ -57,7 +60,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave % WN;
 
     int64_t tm, tn;
     if (LOWER) {
@@ -81,49 +84,75 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     const TI* Hp = (const TI*)g.Ahead;
     const TI* Bp = (const TI*)g.B;
 
+    // Thread-constant parts of the load coordinates.  A element p of this
+    // thread is (row mA + p*ASTEP, k kA) for MK or (row mA, k kA + p*ASTEP)
+    // for KM; likewise for B.
+    const int mA = AKM ? tid % BM : tid / BK;
+    const int kA = AKM ? tid / BM : tid % BK;
+    const int nB = BNK ? tid / BK : tid % BN;
+    const int kB = BNK ? tid % BK : tid / BN;
+    // 32-bit element offsets from the chunk's base pointers (tile-local)
+    int offA[LA], offB[LB];
+    bool vA[LA], vB[LB];
+#pragma unroll
+    for (int p = 0; p < LA; ++p) {
+        const int r = AKM ? kA + p * ASTEP : mA + p * ASTEP;   // stored row within the chunk/tile
+        const int c = AKM ? mA : kA;
+        offA[p] = (int)(r * g.lda + c);
+        vA[p] = AKM ? (m0 + mA < g.M) : (m0 + mA + p * ASTEP < g.M);
+    }
+#pragma unroll
+    for (int p = 0; p < LB; ++p) {
+        const int r = BNK ? nB + p * BSTEP : kB + p * BSTEP;
+        const int c = BNK ? kB : nB;
+        offB[p] = (int)(r * g.ldb + c);
+        vB[p] = BNK ? (n0 + nB + p * BSTEP < g.N) : (n0 + nB < g.N);
+    }
+
     TI ra[LA], rb[LB];
 
     auto load = [&](int64_t k0) {
+        // A
+        if (AKM && k0 < g.head_k) {
+            // chunk touches the head segment: per-element source selection
 #pragma unroll
-        for (int p = 0; p < LA; ++p) {
-            const int idx = tid + p * NT;
-            const int kk = AKM ? idx / BM : idx % BK;
-            const int mm = AKM ? idx % BM : idx / BK;
-            const int64_t gm = m0 + mm, gk = k0 + kk;
-            TI v = (TI)0;
-            const bool upper = g.a_lower && (AKM ? gm > gk : gk > gm);
-            if (gm < g.M && gk < kend && !upper) {
-                if (!AKM) v = Ap[gm * g.lda + gk];
-                else if (gk < g.head_k) v = Hp[gk * g.ldah + gm];
-                else v = Ap[(gk - g.head_k) * g.lda + gm];
+            for (int p = 0; p < LA; ++p) {
+                const int64_t gk = k0 + kA + p * ASTEP, gm = m0 + mA;
+                TI v = (TI)0;
+                if (vA[p] && gk < kend) {
+                    const bool up = g.a_lower && gm > gk;
+                    if (!up) v = gk < g.head_k ? Hp[gk * g.ldah + gm] : Ap[(gk - g.head_k) * g.lda + gm];
+                }
+                ra[p] = v;
             }
-            ra[p] = v;
+        } else {
+            const TI* base = AKM ? Ap + (k0 - g.head_k) * g.lda + m0 : Ap + m0 * g.lda + k0;
+#pragma unroll
+            for (int p = 0; p < LA; ++p) {
+                const int64_t gk = AKM ? k0 + kA + p * ASTEP : k0 + kA;
+                const int64_t gm = AKM ? m0 + mA : m0 + mA + p * ASTEP;
+                const bool ok = vA[p] && gk < kend && !(g.a_lower && (AKM ? gm > gk : gk > gm));
+                ra[p] = ok ? base[offA[p]] : (TI)0;
+            }
         }
+        // B
+        const TI* bbase = BNK ? Bp + n0 * g.ldb + k0 : Bp + k0 * g.ldb + n0;
 #pragma unroll
         for (int p = 0; p < LB; ++p) {
-            const int idx = tid + p * NT;
-            const int kk = BNK ? idx % BK : idx / BN;
-            const int nn = BNK ? idx / BK : idx % BN;
-            const int64_t gn = n0 + nn, gk = k0 + kk;
-            TI v = (TI)0;
-            if (gn < g.N && gk < kend) v = BNK ? Bp[gn * g.ldb + gk] : Bp[gk * g.ldb + gn];
-            rb[p] = v;
+            const int64_t gk = BNK ? k0 + kB : k0 + kB + p * BSTEP;
+            rb[p] = (vB[p] && gk < kend) ? bbase[offB[p]] : (TI)0;
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int p = 0; p < LA; ++p) {
-            const int idx = tid + p * NT;
-            const int kk = AKM ? idx / BM : idx % BK;
-            const int mm = AKM ? idx % BM : idx / BK;
-            sA[buf][kk][mm] = ra[p];
+            if (AKM) sA[buf][kA + p * ASTEP][mA] = ra[p];
+            else sA[buf][kA][mA + p * ASTEP] = ra[p];
         }
 #pragma unroll
         for (int p = 0; p < LB; ++p) {
-            const int idx = tid + p * NT;
-            const int kk = BNK ? idx % BK : idx / BN;
-            const int nn = BNK ? idx / BK : idx % BN;
-            sB[buf][kk][nn] = rb[p];
+            if (BNK) sB[buf][kB][nB + p * BSTEP] = rb[p];
+            else sB[buf][kB + p * BSTEP][nB] = rb[p];
         }
     };
 
@@ -134,12 +163,12 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         for (int j = 0; j < FN; ++j)
             acc[i][j] = acc_t{0, 0, 0, 0};
 
+    const int lr = lane >> 4, lc = lane & 15;
     const int64_t nchunk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
     if (nchunk > 0) {
         load(kbeg);
         store(0);
         __syncthreads();
-        const int lr = lane >> 4, lc = lane & 15;
         for (int64_t c = 0; c < nchunk; ++c) {
             const int cur = (int)(c & 1);
             if (c + 1 < nchunk) load(kbeg + (c + 1) * BK);
@@ -162,7 +191,6 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     }
 
     // epilogue
-    const int lr = lane >> 4, lc = lane & 15;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -178,6 +206,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
                     g.C[row * g.ldc + col] -= v;
                 } else if (EPI == EPI_STORE) {
                     g.C[row * g.ldc + col] = v;
+                    if (g.Cf) g.Cf[row * g.ldcf + col] = (float)v;
                 } else if (EPI == EPI_PARTIAL) {
                     g.C[(int64_t)blockIdx.z * g.pstride + row * g.ldc + col] = v;
                 } else if (EPI == EPI_SYMLOW) {
@@ -187,12 +216,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
                     }
                 } else {  // EPI_PHI
                     g.C[row * g.ldc + col] = v;
+                    if (g.Cf) g.Cf[row * g.ldcf + col] = (float)v;
                     g.C2[row * g.ldc2 + col] = row > col ? v : (row == col ? 0.5 * v : 0.0);
                 }
             }
 }
 
-template <typename TI, int BM, int BN, int BK, bool AKM, bool BNK, int EPI, bool LOWER>
+template <typename TI, int BM, int BN, int BK, int WM, int WN, bool AKM, bool BNK, int EPI, bool LOWER>
 hipError_t launch(hipStream_t s, const GemmArgs& g, int splits)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
@@ -204,7 +234,7 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits)
         tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     }
     dim3 grid((unsigned)tiles, 1, (unsigned)(splits < 1 ? 1 : splits));
-    hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, BK, AKM, BNK, EPI, LOWER>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>), grid, dim3(WM * WN * 64), 0, s, g);
     return hipGetLastError();
 }
 
@@ -212,7 +242,7 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits)
 
 #define GPC_GEMM_CASE(TI, CFG, BM, BN, BK, AKM, BNK, EPI, LOWER)                                 \
     if (cfg == CFG && a_km == AKM && b_nk == BNK && epi == EPI && lower_tiles == LOWER)           \
-        return launch<TI, BM, BN, BK, AKM, BNK, EPI, LOWER>(s, g, splits);
+        return launch<TI, BM, BN, BK, (BM == 128 ? 2 : 2), (BM == 128 ? 4 : 2), AKM, BNK, EPI, LOWER>(s, g, splits);
 
 hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, bool lower_tiles,
                     const GemmArgs& g, int splits)

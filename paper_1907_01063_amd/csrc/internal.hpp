@@ -9,6 +9,8 @@ namespace gpc {
 
 // Largest diagonal block handled inside one workgroup's LDS.
 constexpr int kDiagMax = 128;
+// Largest input dimension of the GP covariance kernels.
+constexpr int kMaxGpDim = 16;
 
 // ---- GEMM on MFMA ---------------------------------------------------------
 // acc[m][n] = sum_{k in [k0,k1)} Aop[m][k] * Bop[k][n], then an epilogue.
@@ -35,6 +37,7 @@ struct GemmArgs {
     int64_t kchunk;     // split-K chunk (multiple of the kernel's BK); splits = gridDim.z
     int64_t pstride;    // EPI_PARTIAL slice stride (elements)
     int32_t a_lower;    // nonzero: A is lower-triangular as stored; its strict upper is never read
+    float* Cf; int64_t ldcf;  // EPI_STORE / EPI_PHI: optional FP32 copy of the stored C (nullptr = none)
 };
 
 enum TileCfg : int { TILE_128 = 0, TILE_64 = 1 };
@@ -58,6 +61,8 @@ hipError_t trtri_diag_batched(hipStream_t s, int64_t n, int b, const double* L, 
                               double* Dinv);
 
 // ---- elementwise helpers ---------------------------------------------------
+// Lf[i][j] = (float)L[i][j] for j < i (strict lower triangle only).
+hipError_t convert_lower_f32(hipStream_t s, int64_t n, const double* L, int64_t ldl, float* Lf, int64_t ldf);
 hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v);
 hipError_t zero_strict_upper(hipStream_t s, int64_t n, double* A, int64_t lda);
 // C[m][n] -= sum_{z<S} P[z*pstride + m*N + n], z increasing.
@@ -75,5 +80,24 @@ hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const
                         int64_t ldl, const double* Dinv, int b, double* B, int64_t ldb, double* Y);
 // *out = 2 * sum_i log L_ii (fixed summation order).
 hipError_t logdet(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* out);
+
+// ---- GP pieces and refinement (gp.hip) -------------------------------------
+// theta (device): (s2, l_1..l_d, sn2).  K, Lbar: lower + zero upper written.
+hipError_t gp_kgen_se(hipStream_t s, int64_t n, int d, const double* X, const double* theta, double* K, int64_t ldk);
+hipError_t gp_lbar(hipStream_t s, int64_t n, const double* L, int64_t ldl, const double* alpha, const double* z,
+                   double* Lbar, int64_t ldlb);
+int64_t gp_hypergrad_parts(int64_t n, int d);   // doubles of workspace for gp_hypergrad_se
+hipError_t gp_hypergrad_se(hipStream_t s, int64_t n, int d, const double* X, const double* theta, const double* Ab,
+                           int64_t ldab, const double* scale, double* grad, double* part);
+hipError_t gp_value(hipStream_t s, int64_t n, const double* z, const double* logdet, double* f);
+int64_t symv_parts(int64_t n);                  // doubles of workspace for symv_lower
+// out = y + sgn * K x  (K symmetric from its lower triangle; absk: |K|; x null: ones; y null: 0)
+hipError_t symv_lower(hipStream_t s, int64_t n, const double* K, int64_t ldk, const double* x, int absk,
+                      const double* y, double sgn, double* out, double* part);
+hipError_t refine_eta(hipStream_t s, int64_t n, const double* r, const double* x, const double* y,
+                      const double* rowabs, double* eta);
+hipError_t vec_axpy(hipStream_t s, int64_t n, const double* d, double* x);
+hipError_t vec_copy(hipStream_t s, int64_t n, const double* a, double* b);
+hipError_t vec_zero(hipStream_t s, int64_t n, double* a);
 
 }  // namespace gpc

@@ -1,0 +1,69 @@
+"""GP marginal log-likelihood as a torch.autograd.Function over the library.
+
+f(theta) = -1/2 y^T K^-1 y - 1/2 log|K|   (the constant -n/2 log 2 pi omitted)
+with K the squared-exponential ARD covariance of X plus noise,
+theta = (s2, l_1..l_d, sn2).  Forward: K -> factor L -> z, alpha, log|K| -> f.
+Backward: Lbar = tril(alpha z^T) - diag(1/L_ii) -> Abar (reverse-mode adjoint of
+the factor, section 3.3.2) -> df/dtheta.  Every step runs in the library's HIP
+kernels; this module only moves tensors between the calls.
+"""
+from __future__ import annotations
+
+import torch
+
+from .gpchol import GPC_FP64, GPC_MIXED, GpcError, Handle, default_handle
+
+
+class NotPositiveDefiniteError(ValueError):
+    def __init__(self, col: int):
+        super().__init__(f"covariance is not positive definite (first failing column {col})")
+        self.col = col
+
+
+def _factor(H: Handle, X, theta, precision):
+    K = H.gp_kgen_se(X, theta)
+    H.set_options(precision=precision)
+    info = H.factor(K)
+    return K, info
+
+
+class GPMarginalLogLik(torch.autograd.Function):
+    """apply(X, y, theta, precision=GPC_FP64, recompute_L=False, handle=None, check=True) -> f
+
+    recompute_L: do not keep L between forward and backward; refactor it
+    (same kernels, same inputs, so the gradient is bitwise the same).
+    check: read the factor's info flag (one device sync) and raise
+    NotPositiveDefiniteError on failure.
+    """
+
+    @staticmethod
+    def forward(ctx, X, y, theta, precision=GPC_FP64, recompute_L=False, handle=None, check=True):
+        H = handle or default_handle(X.device)
+        X = X.detach().contiguous()
+        y = y.detach().contiguous()
+        th = theta.detach().contiguous()
+        L, info = _factor(H, X, th, precision)
+        if check:
+            col = int(info.item())
+            if col != 0:
+                raise NotPositiveDefiniteError(col)
+        f, z, alpha, _ = H.gp_value(L, y)
+        ctx.H, ctx.precision, ctx.recompute = H, precision, recompute_L
+        ctx.save_for_backward(X, th, z, alpha, None if recompute_L else L)
+        return f
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        X, th, z, alpha, L = ctx.saved_tensors
+        H = ctx.H
+        if L is None:
+            L, _ = _factor(H, X, th, ctx.precision)
+        H.set_options(precision=ctx.precision)
+        Lbar = H.gp_lbar(L, alpha, z)
+        H.adjoint(L, Lbar)
+        g = H.gp_hypergrad_se(X, th, Lbar, scale=grad_f.detach().to(torch.float64).contiguous())
+        return None, None, g, None, None, None, None
+
+
+def gp_mll(X, y, theta, precision=GPC_FP64, recompute_L=False, handle=None, check=True):
+    return GPMarginalLogLik.apply(X, y, theta, precision, recompute_L, handle, check)

@@ -25,6 +25,7 @@ GPC_NOTRANS, GPC_TRANS = 0, 1
 EXPORTS = (
     "gpc_create", "gpc_destroy", "gpc_set_stream", "gpc_set_options", "gpc_get_options",
     "gpc_factor", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
+    "gpc_solve_refined", "gpc_gp_kgen_se", "gpc_gp_value", "gpc_gp_lbar", "gpc_gp_hypergrad_se",
     "gpc_trace_enable", "gpc_trace_reset", "gpc_trace_read",
     "gpc_status_string", "gpc_last_error",
 )
@@ -68,6 +69,11 @@ def load_library(path: str = LIB_PATH):
         "gpc_adjoint": [_vp, _i64, _vp, _i64, _vp, _i64],
         "gpc_trsm": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64],
         "gpc_logdet": [_vp, _i64, _vp, _i64, _vp],
+        "gpc_solve_refined": [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
+        "gpc_gp_kgen_se": [_vp, _i64, _i32, _vp, _vp, _vp, _i64],
+        "gpc_gp_value": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp],
+        "gpc_gp_lbar": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64],
+        "gpc_gp_hypergrad_se": [_vp, _i64, _i32, _vp, _vp, _vp, _i64, _vp, _vp],
         "gpc_trace_enable": [_vp, _i32],
         "gpc_trace_reset": [_vp],
         "gpc_trace_read": [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
@@ -174,6 +180,63 @@ class Handle:
         self._check(self.lib.gpc_trsm(self.h, GPC_TRANS if trans else GPC_NOTRANS, n, B2.shape[1],
                                       _ptr(L), ldl, _ptr(B2), ldb), "gpc_trsm")
         return B
+
+    def solve_refined(self, K: torch.Tensor, L: torch.Tensor, y: torch.Tensor, x: torch.Tensor | None = None,
+                      check: bool = True):
+        """x solving K x = y by FP64 refinement with the factor L.  Returns
+        (x, iters, eta) with iters/eta as device scalars.  With check=True a
+        non-converged refinement raises GpcError(GPC_ERR_REFINE)."""
+        ldk, ldl = _mat(K, "K"), _mat(L, "L")
+        n = K.shape[0]
+        if x is None:
+            x = torch.empty_like(y)
+        iters = torch.empty((), dtype=torch.int32, device=K.device)
+        eta = torch.empty((), dtype=torch.float64, device=K.device)
+        self._sync_stream()
+        st = self.lib.gpc_solve_refined(self.h, n, _ptr(K), ldk, _ptr(L), ldl, _ptr(y), _ptr(x),
+                                        _ptr(iters), _ptr(eta))
+        if not (st == GPC_ERR_REFINE and not check):
+            self._check(st, "gpc_solve_refined")
+        return x, iters, eta
+
+    def gp_kgen_se(self, X: torch.Tensor, theta: torch.Tensor, K: torch.Tensor | None = None) -> torch.Tensor:
+        n, d = X.shape
+        if K is None:
+            K = torch.empty((n, n), dtype=torch.float64, device=X.device)
+        self._sync_stream()
+        self._check(self.lib.gpc_gp_kgen_se(self.h, n, d, _ptr(X.contiguous()), _ptr(theta.contiguous()),
+                                            _ptr(K), _mat(K, "K")), "gpc_gp_kgen_se")
+        return K
+
+    def gp_value(self, L: torch.Tensor, y: torch.Tensor):
+        """(f, z, alpha, logdet) of the GP log-density from the factor L."""
+        n = L.shape[0]
+        z, alpha = torch.empty_like(y), torch.empty_like(y)
+        ld = torch.empty((), dtype=torch.float64, device=L.device)
+        f = torch.empty((), dtype=torch.float64, device=L.device)
+        self._sync_stream()
+        self._check(self.lib.gpc_gp_value(self.h, n, _ptr(L), _mat(L, "L"), _ptr(y), _ptr(z), _ptr(alpha),
+                                          _ptr(ld), _ptr(f)), "gpc_gp_value")
+        return f, z, alpha, ld
+
+    def gp_lbar(self, L: torch.Tensor, alpha: torch.Tensor, z: torch.Tensor, Lbar: torch.Tensor | None = None):
+        n = L.shape[0]
+        if Lbar is None:
+            Lbar = torch.empty_like(L)
+        self._sync_stream()
+        self._check(self.lib.gpc_gp_lbar(self.h, n, _ptr(L), _mat(L, "L"), _ptr(alpha), _ptr(z), _ptr(Lbar),
+                                         _mat(Lbar, "Lbar")), "gpc_gp_lbar")
+        return Lbar
+
+    def gp_hypergrad_se(self, X: torch.Tensor, theta: torch.Tensor, Abar: torch.Tensor,
+                        scale: torch.Tensor | None = None) -> torch.Tensor:
+        n, d = X.shape
+        grad = torch.empty(d + 2, dtype=torch.float64, device=X.device)
+        self._sync_stream()
+        self._check(self.lib.gpc_gp_hypergrad_se(self.h, n, d, _ptr(X.contiguous()), _ptr(theta.contiguous()),
+                                                 _ptr(Abar), _mat(Abar, "Abar"), _ptr(scale), _ptr(grad)),
+                    "gpc_gp_hypergrad_se")
+        return grad
 
     def trace_enable(self, on: bool = True):
         self._check(self.lib.gpc_trace_enable(self.h, 1 if on else 0), "gpc_trace_enable")

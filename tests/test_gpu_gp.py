@@ -1,0 +1,124 @@
+"""GP layer on the GPU: covariance, log-density value, Lbar, hyper-gradient and
+the autograd.Function, against the oracle (FP64, 1e-11), finite differences
+and torch.autograd.gradcheck."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from gpu_util import TOL, dev, host, relf, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1907_01063_amd import Handle
+    return Handle()
+
+
+def _inputs(n, d, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, d))
+    y = rng.standard_normal(n)
+    theta = np.concatenate([[1.3], rng.uniform(0.8, 2.5, size=d), [0.1]])
+    return x, y, theta
+
+
+@pytest.mark.parametrize("n,d", [(1, 1), (31, 3), (200, 8), (333, 16)])
+def test_kgen_parity(H, n, d):
+    x, _, th = _inputs(n, d, n)
+    say(f"kgen n={n} d={d}")
+    K = H.gp_kgen_se(dev(x), dev(th))
+    Ko = oracle.gp_kgen_se(x, th[0], th[1:1 + d], th[-1])
+    assert np.all(np.triu(host(K), 1) == 0.0)
+    assert relf(host(K), Ko) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [5, 200, 513])
+def test_value_lbar_hypergrad_parity(H, n):
+    d = 4
+    x, y, th = _inputs(n, d, 40 + n)
+    Ko = oracle.gp_kgen_se(x, th[0], th[1:1 + d], th[-1])
+    Lo, info = oracle.potrf(Ko)
+    assert info == 0
+    fo, zo, ao, ldo = oracle.gp_mll(Lo, y)
+    say(f"gp value n={n}")
+    L = dev(Lo)
+    f, z, a, ld = H.gp_value(L, dev(y))
+    assert abs(float(host(f)) - fo) <= TOL * abs(fo)
+    assert abs(float(host(ld)) - ldo) <= TOL * abs(ldo)
+    assert relf(host(z), zo) <= TOL and relf(host(a), ao) <= TOL
+    Lb = H.gp_lbar(L, dev(ao), dev(zo))
+    assert relf(host(Lb), oracle.gp_lbar(Lo, ao, zo)) <= TOL
+    # hyper-gradient on a shared seeded Abar input
+    Ab = W.lower_normal(np.random.default_rng(n), n)
+    scale = torch.tensor(0.75, dtype=torch.float64, device="cuda")
+    g = H.gp_hypergrad_se(dev(x), dev(th), dev(Ab), scale=scale)
+    go = 0.75 * oracle.gp_hypergrad_se(x, th[0], th[1:1 + d], Ab)
+    assert relf(host(g), go) <= TOL
+
+
+@pytest.mark.parametrize("n", [64, 300])
+def test_autograd_mll_matches_oracle_chain(H, n):
+    from paper_1907_01063_amd import gp_mll
+    d = 3
+    x, y, th = _inputs(n, d, 70 + n)
+    theta = dev(th).requires_grad_(True)
+    say(f"autograd mll n={n}")
+    f = gp_mll(dev(x), dev(y), theta, handle=H)
+    f.backward()
+    Ko = oracle.gp_kgen_se(x, th[0], th[1:1 + d], th[-1])
+    Lo, _ = oracle.potrf(Ko)
+    fo, zo, ao, _ = oracle.gp_mll(Lo, y)
+    Abo = oracle.potrf_adjoint(Lo, oracle.gp_lbar(Lo, ao, zo))
+    go = oracle.gp_hypergrad_se(x, th[0], th[1:1 + d], Abo)
+    assert abs(float(host(f)) - fo) <= TOL * abs(fo)
+    assert relf(host(theta.grad), go) <= 1e-10
+
+
+def test_autograd_gradcheck_small(H):
+    from paper_1907_01063_amd import gp_mll
+    x, y, th = _inputs(24, 2, 5)
+    X, Y = dev(x), dev(y)
+    theta = dev(th).requires_grad_(True)
+    say("gradcheck")
+    assert torch.autograd.gradcheck(lambda t: gp_mll(X, Y, t, handle=H), (theta,), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_recompute_L_is_bitwise_identical(H):
+    from paper_1907_01063_amd import gp_mll
+    x, y, th = _inputs(400, 5, 9)
+    grads = []
+    for rec in (False, True):
+        theta = dev(th).requires_grad_(True)
+        gp_mll(dev(x), dev(y), theta, recompute_L=rec, handle=H).backward()
+        grads.append(host(theta.grad))
+    assert np.array_equal(grads[0], grads[1])
+
+
+def test_not_positive_definite_raises(H):
+    from paper_1907_01063_amd import NotPositiveDefiniteError, gp_mll
+    x = np.zeros((10, 2))          # identical points, no noise: rank one
+    th = np.array([1.0, 1.0, 1.0, 0.0])
+    with pytest.raises(NotPositiveDefiniteError) as ei:
+        gp_mll(dev(x), dev(np.ones(10)), dev(th), handle=H)
+    assert ei.value.col == 2
+
+
+def test_mixed_mll_gradient_error_budget(H):
+    from paper_1907_01063_amd import GPC_MIXED, gp_mll
+    d = 4
+    x, y, th = _inputs(600, d, 11)
+    theta = dev(th).requires_grad_(True)
+    f = gp_mll(dev(x), dev(y), theta, precision=GPC_MIXED, handle=H)
+    f.backward()
+    H.set_options(precision=0)
+    Ko = oracle.gp_kgen_se(x, th[0], th[1:1 + d], th[-1])
+    Lo, _ = oracle.potrf(Ko)
+    fo, zo, ao, _ = oracle.gp_mll(Lo, y)
+    go = oracle.gp_hypergrad_se(x, th[0], th[1:1 + d], oracle.potrf_adjoint(Lo, oracle.gp_lbar(Lo, ao, zo)))
+    ef, eg = abs(float(host(f)) - fo) / abs(fo), relf(host(theta.grad), go)
+    say(f"mixed mll: f err {ef:.2e}, grad err {eg:.2e}")
+    assert ef <= 1e-3 and eg <= 1e-2

@@ -1,0 +1,112 @@
+"""Mixed form (FP32 MFMA trailing updates, FP64 diagonal blocks and panels) and
+FP64 iterative refinement, against the FP64 oracle.
+
+The mixed factor and adjoint have no oracle of their own (parity unpinned):
+their error against the FP64 oracle is reported and bounded by a budget
+derived from the arithmetic: FP32 products carry unit roundoff 2^-24 = 6e-8
+per trailing update, amplified by the conditioning of the matrix (about 1e3 to
+1e4 here), so errors of order 1e-4 and below are expected; the tests allow
+1e-3 (L) and 1e-2 (Abar).  The refined solve is pinned: its normwise backward
+error must reach 1e-12 and its solution must match the oracle's FP64 solve to
+the conditioning-limited accuracy.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from gpu_util import TOL, dev, host, relf, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1907_01063_amd import Handle
+    return Handle()
+
+
+def mixed(H):
+    from paper_1907_01063_amd import GPC_MIXED
+    H.set_options(precision=GPC_MIXED)
+
+
+def fp64(H):
+    from paper_1907_01063_amd import GPC_FP64
+    H.set_options(precision=GPC_FP64)
+
+
+@pytest.mark.parametrize("n", [100, 129, 300, 700, 1000])
+def test_mixed_factor_and_adjoint_error_budget(H, n):
+    case = W.c3(n=n)
+    say(f"mixed factor+adjoint n={n}")
+    mixed(H)
+    At = dev(case["A"])
+    info = H.factor(At)
+    Lbt = dev(case["Lbar"])
+    H.adjoint(At, Lbt)
+    fp64(H)
+    Lo, _ = oracle.potrf(case["A"])
+    Ao = oracle.potrf_adjoint(Lo, case["Lbar"])
+    eL, eA = relf(host(At), Lo), relf(host(Lbt), Ao)
+    say(f"  mixed n={n}: L err {eL:.2e}, Abar err {eA:.2e}")
+    assert int(host(info)) == 0
+    assert np.all(np.triu(host(At), 1) == 0.0) and np.all(np.triu(host(Lbt), 1) == 0.0)
+    assert eL <= 1e-3 and eA <= 1e-2
+    if n <= 128:          # a single diagonal block: no FP32 update at all
+        assert eL <= TOL
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [257, 1000])
+def test_refined_solve(H, form, n):
+    case = W.c3(n=n)
+    say(f"refine {form} n={n}")
+    (mixed if form == "mixed" else fp64)(H)
+    L = dev(case["A"])
+    H.factor(L)
+    fp64(H)
+    K = dev(case["A"])
+    y = dev(case["y"])
+    x, iters, eta = H.solve_refined(K, L, y)
+    it, e = int(host(iters)), float(host(eta))
+    Lo, _ = oracle.potrf(case["A"])
+    xo = oracle.trsm(Lo, oracle.trsm(Lo, case["y"]), trans=True)
+    err = relf(host(x), xo)
+    say(f"  {form}: iters {it}, eta {e:.2e}, |x - x_oracle|/|x_oracle| {err:.2e}")
+    assert e <= 1e-12
+    assert 1 <= it <= (2 if form == "fp64" else 6)
+    # the oracle's own solve is exact up to cond * 1e-16; allow that slack
+    assert err <= 1e-9
+
+
+def test_refined_solve_reports_nonconvergence(H):
+    from paper_1907_01063_amd.gpchol import GPC_ERR_REFINE, GpcError
+    case = W.c3(n=300)
+    mixed(H)
+    L = dev(case["A"])
+    H.factor(L)
+    H.set_options(precision=0, refine_maxit=1, refine_tol=1e-300)
+    try:
+        with pytest.raises(GpcError) as ei:
+            H.solve_refined(dev(case["A"]), L, dev(case["y"]))
+        assert ei.value.status == GPC_ERR_REFINE
+        x, iters, eta = H.solve_refined(dev(case["A"]), L, dev(case["y"]), check=False)
+        assert int(host(iters)) == 1
+    finally:
+        H.set_options(precision=0, refine_maxit=10, refine_tol=1e-12)
+
+
+def test_mixed_adjoint_given_factor_matches_fp64_closely(H):
+    # the mixed adjoint only rounds its two trailing products to FP32
+    rng = np.random.default_rng(33)
+    _, L0 = W.spd_from_factor(rng, 400)
+    Lb = W.lower_normal(rng, 400)
+    mixed(H)
+    Lbt = dev(Lb)
+    H.adjoint(dev(L0), Lbt)
+    fp64(H)
+    e = relf(host(Lbt), oracle.potrf_adjoint(L0, Lb))
+    say(f"mixed adjoint given factor: {e:.2e}")
+    assert e <= 1e-4
