@@ -148,6 +148,36 @@ gpc_status gpc_gp_lbar(gpc_handle* h, int64_t n, const double* L, int64_t ldl, c
 gpc_status gpc_gp_hypergrad_se(gpc_handle* h, int64_t n, int32_t d, const double* X, const double* theta,
                                const double* Abar, int64_t ldab, const double* scale_dev, double* grad_dev);
 
+/* Batched forms: nb matrices of uneven order n_host[i] (>= 0), each stored
+ * row-major with leading dimension n_host[i] at element offset off_host[i]
+ * from the base pointer (the caller keeps them disjoint).  One persistent
+ * launch handles the whole batch: workgroups take matrices from a device
+ * queue, largest first, and factor / differentiate each alone (the same
+ * blocked algorithms as gpc_factor / gpc_adjoint, inner block chosen per size
+ * bucket by gpc_autotune_batched, default 64).  The launch is captured once
+ * into a HIP graph per distinct (sizes, offsets, pointers) and replayed on
+ * later calls; if the handle's stream is itself being captured, the launch is
+ * recorded into the caller's graph instead.  Results are bitwise independent
+ * of queue order.  info_dev: nb device int32 (0 or first failing column + 1).
+ * FP64 only. */
+gpc_status gpc_factor_batched(gpc_handle* h, int32_t nb, const int32_t* n_host, const int64_t* off_host,
+                              double* base, int32_t* info_dev);
+gpc_status gpc_adjoint_batched(gpc_handle* h, int32_t nb, const int32_t* n_host, const int64_t* off_host,
+                               const double* Lbase, double* Lbarbase);
+/* Factor then adjoint of every matrix in one launch (Lbar given, Abar out). */
+gpc_status gpc_factor_adjoint_batched(gpc_handle* h, int32_t nb, const int32_t* n_host, const int64_t* off_host,
+                                      double* base, double* Lbarbase, int32_t* info_dev);
+
+/* Autotuner of the batched path: for each size bucket (n < 128, 256, 512,
+ * 1024, larger) time factor+adjoint of a synthetic diagonally dominant batch
+ * with inner blocks 32 and 64 (median of 3) and keep the faster.  If
+ * cache_path is not NULL the choices are written there; handles read the file
+ * named by the environment variable GPC_TUNE_CACHE at creation.  Waits for
+ * the stream.  gpc_get_tuning returns the 5 bucket blocks and whether they
+ * come from tuning. */
+gpc_status gpc_autotune_batched(gpc_handle* h, const char* cache_path);
+gpc_status gpc_get_tuning(const gpc_handle* h, int32_t* blocks_out, int32_t* tuned);
+
 /* Kernel classes reported by the launch trace below. */
 typedef enum {
     GPC_K_DIAG_FACTOR = 0,      /* diagonal-block factor + inverse (one workgroup) */
@@ -160,7 +190,8 @@ typedef enum {
     GPC_K_ADJ_DIAG_BLOCK = 7,   /* Dbar <- Phi(D^-T sym(D^T Dbar) D^-1) (4 launches) */
     GPC_K_ADJ_ROW_UPDATE = 8,   /* split-K slices of [M; Cbar]^T [R; B] */
     GPC_K_REDUCE = 9,           /* fixed-order sum of split-K slices into Rbar */
-    GPC_K_COUNT = 10
+    GPC_K_BATCHED = 10,         /* one persistent batched launch (graph replay) */
+    GPC_K_COUNT = 11
 } gpc_kernel_class;
 
 /* Launch trace, for measurement: while enabled, every launch of the classes

@@ -17,8 +17,32 @@ struct TraceRec {
     double flops, bytes;
 };
 
+// Size buckets of the batched path's tuned inner block.
+constexpr int kTuneBuckets = 5;
+constexpr int kTuneLimits[kTuneBuckets] = {128, 256, 512, 1024, 1 << 30};   // n < limit
+
+struct BatchPlan {
+    int mode = 0;
+    const void *A = nullptr, *Lb = nullptr, *info = nullptr;
+    std::vector<int32_t> n;
+    std::vector<int64_t> off;
+    std::vector<int32_t> blocks;   // tuned block per bucket when the plan was made
+    gpc::BatchTask* d_tasks = nullptr;
+    int32_t* d_counter = nullptr;
+    double* d_ws = nullptr;
+    int wgs = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double flops = 0.0;
+};
+
 struct gpc_handle {
     int device = 0;
+    int cus = 256;
+    int tune_block[kTuneBuckets] = {64, 64, 64, 64, 64};
+    bool tuned = false;
+    hipStream_t cap_stream = nullptr;    // private stream used only to capture graphs
+    BatchPlan* plan = nullptr;
     hipStream_t stream = nullptr;
     gpc_options opt{};
     void* ws = nullptr;
@@ -103,6 +127,43 @@ struct Traced {
     }
 };
 
+void free_plan(BatchPlan* p)
+{
+    if (!p) return;
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->d_tasks) hipFree(p->d_tasks);
+    if (p->d_counter) hipFree(p->d_counter);
+    if (p->d_ws) hipFree(p->d_ws);
+    delete p;
+}
+
+int bucket_of(int32_t n)
+{
+    for (int b = 0; b < kTuneBuckets; ++b)
+        if (n < kTuneLimits[b]) return b;
+    return kTuneBuckets - 1;
+}
+
+// Tuning cache: lines "<arch> <precision> <bucket-limit> <block>".
+void load_tune_cache(gpc_handle* h, const char* path)
+{
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    int prec, lim, blk;
+    while (fscanf(f, "%63s %d %d %d", arch, &prec, &lim, &blk) == 4) {
+        if (strcmp(arch, "gfx950") != 0 || prec != GPC_FP64) continue;
+        for (int b = 0; b < kTuneBuckets; ++b)
+            if (kTuneLimits[b] == lim && (blk == 32 || blk == 64)) {
+                h->tune_block[b] = blk;
+                h->tuned = true;
+            }
+    }
+    fclose(f);
+}
+
 int block_of(const gpc_handle* h) { return h->opt.block > 0 ? h->opt.block : kDefaultBlock; }
 
 bool ld_ok(int64_t n, int64_t ld) { return ld >= std::max<int64_t>(1, n); }
@@ -173,6 +234,8 @@ gpc_status gpc_create(gpc_handle** out, void* stream)
     h->opt.lookahead = 0;
     h->opt.refine_maxit = 10;
     h->opt.refine_tol = 1e-12;
+    h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    load_tune_cache(h, getenv("GPC_TUNE_CACHE"));
     *out = h;
     return GPC_OK;
 }
@@ -184,6 +247,8 @@ gpc_status gpc_destroy(gpc_handle* h)
     if (hipStreamSynchronize(h->stream) != hipSuccess) st = GPC_ERR_HIP;
     if (h->ws && hipFree(h->ws) != hipSuccess) st = GPC_ERR_HIP;
     for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+    free_plan(h->plan);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     delete h;
     return st;
 }
@@ -584,6 +649,169 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
     }
     GPC_HIP(h, fill_i32(s, iters, it));
     return eta_h <= h->opt.refine_tol ? GPC_OK : GPC_ERR_REFINE;
+}
+
+// --------------------------------------------------------------- batched ---
+namespace {
+
+gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_host, const int64_t* off_host,
+                       double* A, double* Lb, int32_t* info)
+{
+    if (!h || nb < 0 || (nb > 0 && (!n_host || !off_host || !A))) return GPC_ERR_ARG;
+    if ((mode & 1) && nb > 0 && !info) return GPC_ERR_ARG;
+    if ((mode & 2) && nb > 0 && !Lb) return GPC_ERR_ARG;
+    for (int32_t i = 0; i < nb; ++i)
+        if (n_host[i] < 0 || off_host[i] < 0) return GPC_ERR_ARG;
+    if (nb == 0) return GPC_OK;
+    hipStream_t s = h->stream;
+    std::vector<int32_t> blocks(h->tune_block, h->tune_block + kTuneBuckets);
+    BatchPlan* p = h->plan;
+    const bool same = p && p->mode == mode && p->A == A && p->Lb == Lb && p->info == info &&
+                      p->blocks == blocks && p->n.size() == (size_t)nb &&
+                      std::equal(p->n.begin(), p->n.end(), n_host) && std::equal(p->off.begin(), p->off.end(), off_host);
+    if (!same) {
+        GPC_HIP(h, hipStreamSynchronize(s));
+        free_plan(p);
+        h->plan = p = new BatchPlan();
+        p->mode = mode;
+        p->A = A;
+        p->Lb = Lb;
+        p->info = info;
+        p->n.assign(n_host, n_host + nb);
+        p->off.assign(off_host, off_host + nb);
+        p->blocks = blocks;
+        std::vector<gpc::BatchTask> tasks(nb);
+        for (int32_t i = 0; i < nb; ++i) {
+            tasks[i].n = n_host[i];
+            tasks[i].block = h->tune_block[bucket_of(n_host[i])];
+            tasks[i].idx = i;
+            tasks[i].pad = 0;
+            tasks[i].off = off_host[i];
+            const double dn = (double)n_host[i];
+            p->flops += ((mode & 1) ? dn * dn * dn / 3.0 + dn * dn / 2.0 + dn / 6.0 : 0.0) +
+                        ((mode & 2) ? 2.0 * dn * dn * dn / 3.0 : 0.0);
+        }
+        std::stable_sort(tasks.begin(), tasks.end(),
+                         [](const gpc::BatchTask& a, const gpc::BatchTask& b) { return a.n > b.n; });
+        p->wgs = std::min<int>(nb, 2 * h->cus);
+        GPC_HIP(h, hipMalloc(&p->d_tasks, sizeof(gpc::BatchTask) * nb));
+        GPC_HIP(h, hipMalloc(&p->d_counter, sizeof(int32_t)));
+        GPC_HIP(h, hipMalloc(&p->d_ws, sizeof(double) * gpc::batched_scratch_doubles(p->wgs)));
+        GPC_HIP(h, hipMemcpy(p->d_tasks, tasks.data(), sizeof(gpc::BatchTask) * nb, hipMemcpyHostToDevice));
+        if (!h->cap_stream) GPC_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        GPC_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = gpc::batched_launch(h->cap_stream, nb, p->d_tasks, A, Lb, info, p->d_counter, p->d_ws,
+                                            p->wgs, mode);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
+        p->graph = g;
+        if (le != hipSuccess) return hip_fail(h, le, "batched launch (capture)");
+        if (ce != hipSuccess) return hip_fail(h, ce, "hipStreamEndCapture");
+        GPC_HIP(h, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    GPC_HIP(h, hipStreamIsCapturing(s, &cs));
+    Traced t(h, GPC_K_BATCHED, p->flops, 0.0);
+    if (cs == hipStreamCaptureStatusNone) {
+        GPC_HIP(h, hipGraphLaunch(p->exec, s));
+    } else {
+        // the caller is capturing: record the launch into its graph instead
+        GPC_HIP(h, gpc::batched_launch(s, nb, p->d_tasks, A, Lb, info, p->d_counter, p->d_ws, p->wgs, mode));
+    }
+    return GPC_OK;
+}
+
+}  // namespace
+
+gpc_status gpc_factor_batched(gpc_handle* h, int32_t nb, const int32_t* n_host, const int64_t* off_host,
+                              double* base, int32_t* info_dev)
+{
+    return run_batched(h, 1, nb, n_host, off_host, base, nullptr, info_dev);
+}
+
+gpc_status gpc_adjoint_batched(gpc_handle* h, int32_t nb, const int32_t* n_host, const int64_t* off_host,
+                               const double* Lbase, double* Lbarbase)
+{
+    return run_batched(h, 2, nb, n_host, off_host, const_cast<double*>(Lbase), Lbarbase, nullptr);
+}
+
+gpc_status gpc_factor_adjoint_batched(gpc_handle* h, int32_t nb, const int32_t* n_host, const int64_t* off_host,
+                                      double* base, double* Lbarbase, int32_t* info_dev)
+{
+    return run_batched(h, 3, nb, n_host, off_host, base, Lbarbase, info_dev);
+}
+
+// Autotuner of the batched path: for each size bucket, time factor+adjoint of
+// a synthetic batch (16 matrices at the bucket's middle order) with inner
+// blocks 32 and 64 (median of 3 runs each), keep the faster; optionally
+// append the choices to a cache file read by later handles.
+gpc_status gpc_autotune_batched(gpc_handle* h, const char* cache_path)
+{
+    if (!h) return GPC_ERR_ARG;
+    hipStream_t s = h->stream;
+    const int mids[kTuneBuckets] = {80, 192, 384, 768, 1024};
+    const int cnt = 16;
+    for (int bk = 0; bk < kTuneBuckets; ++bk) {
+        const int64_t n = mids[bk];
+        std::vector<int32_t> ns(cnt, (int32_t)n);
+        std::vector<int64_t> offs(cnt);
+        for (int i = 0; i < cnt; ++i) offs[i] = (int64_t)i * n * n;
+        double *A = nullptr, *Lb = nullptr;
+        int32_t* info = nullptr;
+        hipEvent_t e0, e1;
+        GPC_HIP(h, hipMalloc(&A, sizeof(double) * cnt * n * n));
+        GPC_HIP(h, hipMalloc(&Lb, sizeof(double) * cnt * n * n));
+        GPC_HIP(h, hipMalloc(&info, sizeof(int32_t) * cnt));
+        GPC_HIP(h, hipEventCreate(&e0));
+        GPC_HIP(h, hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        int best = h->tune_block[bk];
+        for (int cand : {32, 64}) {
+            h->tune_block[bk] = cand;   // the synthetic batch lies in bucket bk only
+            float t[3];
+            for (int r = 0; r < 3; ++r) {
+                for (int i = 0; i < cnt; ++i) GPC_HIP(h, gpc::spd_test_fill(s, n, A, Lb, offs[i]));
+                GPC_HIP(h, hipEventRecord(e0, s));
+                gpc_status st = run_batched(h, 3, cnt, ns.data(), offs.data(), A, Lb, info);
+                if (st != GPC_OK) return st;
+                GPC_HIP(h, hipEventRecord(e1, s));
+                GPC_HIP(h, hipEventSynchronize(e1));
+                GPC_HIP(h, hipEventElapsedTime(&t[r], e0, e1));
+            }
+            std::sort(t, t + 3);
+            if (t[1] < best_ms) {
+                best_ms = t[1];
+                best = cand;
+            }
+        }
+        h->tune_block[bk] = best;
+        GPC_HIP(h, hipStreamSynchronize(s));
+        free_plan(h->plan);
+        h->plan = nullptr;
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        hipFree(A);
+        hipFree(Lb);
+        hipFree(info);
+    }
+    h->tuned = true;
+    if (cache_path && *cache_path) {
+        FILE* f = fopen(cache_path, "w");
+        if (f) {
+            for (int bk = 0; bk < kTuneBuckets; ++bk)
+                fprintf(f, "gfx950 %d %d %d\n", (int)GPC_FP64, kTuneLimits[bk], h->tune_block[bk]);
+            fclose(f);
+        }
+    }
+    return GPC_OK;
+}
+
+gpc_status gpc_get_tuning(const gpc_handle* h, int32_t* blocks_out, int32_t* tuned)
+{
+    if (!h || !blocks_out || !tuned) return GPC_ERR_ARG;
+    for (int b = 0; b < kTuneBuckets; ++b) blocks_out[b] = h->tune_block[b];
+    *tuned = h->tuned ? 1 : 0;
+    return GPC_OK;
 }
 
 }  // extern "C"

@@ -10,7 +10,7 @@
 // trtri_diag_batched: inverses of all diagonal blocks of a given factor, one
 // workgroup per block (the D^-1 of each step of the reverse sweep, 3.3.2);
 // block q goes to Dinv + q*b*b with leading dimension b.
-#include "internal.hpp"
+#include "diag.hpp"
 
 namespace gpc {
 namespace {
@@ -60,112 +60,11 @@ __device__ void invert_in_lds(double* S, double* xd, int kb)
     __syncthreads();
 }
 
-// Factor + inverse of one diagonal block with the block held in registers.
-// Thread (ty, tx) of a 16 x 16 grid owns the elements (i, c) = (ty + 16a, tx + 16b)
-// with a >= b (the lower triangle, up to 36 per thread) in E[a][b] for the
-// whole kernel.  Step j (one column):
-//   A. the owner of (j, j) takes d = E(j,j), records a failed pivot, publishes
-//      L_jj = sqrt(d) and writes it out;                              barrier
-//   B. owners of column j publish L_ij = E(i,j) / L_jj (i > j) and write them
-//      out, then restart those registers as the inverse's column j; owners of
-//      row j publish the now-final inverse row Xh_jc = X_jc / L_jj (c < j)
-//      and 1 / L_jj, and write them out;                              barrier
-//   C. every thread updates its elements with one multiply-add:
-//      c > j:  E -= L_ij L_cj       (trailing Schur complement)
-//      c <= j: E -= L_ij Xh_jc      (forward substitution of the inverse)
-// so the factor of section 3.3.1's diagonal step and its inverse (used by the
-// panel solve) come out of the same sweep.  E(i, c) for c < j holds the
-// inverse's running entry X_ic once column c of L has been written out.
 __global__ void __launch_bounds__(256)
 potrf_diag_kernel(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info, int64_t col0)
 {
-    __shared__ double colbuf[kDiagMax];
-    __shared__ double rowbuf[kDiagMax];
-    __shared__ double sljj;
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-
-    // strict upper triangles of both outputs are zero
-    for (int idx = tid; idx < kb * kb; idx += 256) {
-        const int r = idx / kb, c = idx % kb;
-        if (c > r) {
-            A[r * lda + c] = 0.0;
-            Linv[r * ldi + c] = 0.0;
-        }
-    }
-
-    double E[8][8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = ty + 16 * a, c = tx + 16 * b;
-            E[a][b] = (i < kb && c <= i) ? A[i * lda + c] : 0.0;
-        }
-
-#pragma unroll
-    for (int aj = 0; aj < 8; ++aj) {
-        if (aj * 16 >= kb) break;
-        for (int rj = 0; rj < 16; ++rj) {
-            const int j = aj * 16 + rj;
-            if (j >= kb) break;
-            // A: pivot
-            if (ty == rj && tx == rj) {
-                const double d = E[aj][aj];
-                if (!(d > 0.0) && *info == 0) *info = (int32_t)(col0 + j + 1);
-                const double l = sqrt(d);
-                sljj = l;
-                A[j * lda + j] = l;
-            }
-            __syncthreads();
-            const double ljj = sljj;
-            const double rl = 1.0 / ljj;
-            // B: publish column j of L and row j of the inverse
-            if (tx == rj) {
-#pragma unroll
-                for (int a = aj; a < 8; ++a) {
-                    const int i = ty + 16 * a;
-                    if (i > j && i < kb) {
-                        const double l = E[a][aj] * rl;
-                        colbuf[i] = l;
-                        A[i * lda + j] = l;
-                        E[a][aj] = 0.0;
-                    }
-                }
-            }
-            if (ty == rj) {
-#pragma unroll
-                for (int b = 0; b <= aj; ++b) {
-                    const int c = tx + 16 * b;
-                    if (c < j) {
-                        const double xh = E[aj][b] * rl;
-                        rowbuf[c] = xh;
-                        Linv[j * ldi + c] = xh;
-                    } else if (c == j) {
-                        rowbuf[j] = rl;
-                        Linv[j * ldi + j] = rl;
-                    }
-                }
-            }
-            __syncthreads();
-            // C: one multiply-add per owned element
-            double g[8], f[8];
-#pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                const int i = ty + 16 * a;
-                g[a] = (i > j && i < kb) ? colbuf[i] : 0.0;
-            }
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const int c = tx + 16 * b;
-                f[b] = c >= kb ? 0.0 : (c > j ? colbuf[c] : rowbuf[c]);
-            }
-#pragma unroll
-            for (int a = 0; a < 8; ++a)
-#pragma unroll
-                for (int b = 0; b <= a; ++b)
-                    E[a][b] -= g[a] * f[b];
-        }
-    }
+    __shared__ double colbuf[kDiagMax], rowbuf[kDiagMax], sljj;
+    diag_factor_inverse<kDiagMax / 16>(kb, A, lda, Linv, ldi, info, col0, colbuf, rowbuf, &sljj);
 }
 
 __global__ void __launch_bounds__(256)

@@ -100,4 +100,20 @@ hipError_t vec_axpy(hipStream_t s, int64_t n, const double* d, double* x);
 hipError_t vec_copy(hipStream_t s, int64_t n, const double* a, double* b);
 hipError_t vec_zero(hipStream_t s, int64_t n, double* a);
 
+// ---- batched persistent path (batched.hip) ----------------------------------
+struct BatchTask {
+    int32_t n;      // matrix order
+    int32_t block;  // inner block (<= batched_max_block())
+    int32_t idx;    // position in the caller's arrays (info index)
+    int32_t pad;
+    int64_t off;    // element offset of the matrix (row-major, leading dimension n)
+};
+int batched_max_block();
+int64_t batched_scratch_doubles(int wgs);
+// mode: 1 = factor, 2 = adjoint (Abase holds L), 3 = both.  counter: one device
+// int32 reset by a kernel at the start (capturable).
+hipError_t batched_launch(hipStream_t s, int nb, const BatchTask* tasks, double* Abase, double* Lbbase,
+                          int32_t* info, int32_t* counter, double* ws, int wgs, int mode);
+hipError_t spd_test_fill(hipStream_t s, int64_t n, double* A, double* Lb, int64_t off);
+
 }  // namespace gpc

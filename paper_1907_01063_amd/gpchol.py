@@ -26,13 +26,16 @@ EXPORTS = (
     "gpc_create", "gpc_destroy", "gpc_set_stream", "gpc_set_options", "gpc_get_options",
     "gpc_factor", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
     "gpc_solve_refined", "gpc_gp_kgen_se", "gpc_gp_value", "gpc_gp_lbar", "gpc_gp_hypergrad_se",
+    "gpc_factor_batched", "gpc_adjoint_batched", "gpc_factor_adjoint_batched", "gpc_autotune_batched",
+    "gpc_get_tuning",
     "gpc_trace_enable", "gpc_trace_reset", "gpc_trace_read",
     "gpc_status_string", "gpc_last_error",
 )
 
 # Kernel classes of the launch trace (gpc_kernel_class).
 KERNEL_CLASSES = ("diag_factor", "panel_solve", "trailing_update", "diag_inverse", "adj_panel_solve",
-                  "adj_left_update", "adj_diag_product", "adj_diag_block", "adj_row_update", "reduce")
+                  "adj_left_update", "adj_diag_product", "adj_diag_block", "adj_row_update", "reduce",
+                  "batched")
 
 
 class GpcError(RuntimeError):
@@ -74,6 +77,11 @@ def load_library(path: str = LIB_PATH):
         "gpc_gp_value": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp],
         "gpc_gp_lbar": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64],
         "gpc_gp_hypergrad_se": [_vp, _i64, _i32, _vp, _vp, _vp, _i64, _vp, _vp],
+        "gpc_factor_batched": [_vp, _i32, _vp, _vp, _vp, _vp],
+        "gpc_adjoint_batched": [_vp, _i32, _vp, _vp, _vp, _vp],
+        "gpc_factor_adjoint_batched": [_vp, _i32, _vp, _vp, _vp, _vp, _vp],
+        "gpc_autotune_batched": [_vp, ctypes.c_char_p],
+        "gpc_get_tuning": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
         "gpc_trace_enable": [_vp, _i32],
         "gpc_trace_reset": [_vp],
         "gpc_trace_read": [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
@@ -237,6 +245,52 @@ class Handle:
                                                  _ptr(Abar), _mat(Abar, "Abar"), _ptr(scale), _ptr(grad)),
                     "gpc_gp_hypergrad_se")
         return grad
+
+    def _batch_args(self, n, off):
+        import numpy as np
+        n_arr = np.ascontiguousarray(np.asarray(n, dtype=np.int32))
+        off_arr = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+        if n_arr.shape != off_arr.shape or n_arr.ndim != 1:
+            raise ValueError("n and off must be 1-D of equal length")
+        self._keep = (n_arr, off_arr)
+        return len(n_arr), n_arr.ctypes.data_as(_vp), off_arr.ctypes.data_as(_vp)
+
+    def factor_batched(self, n, off, base: torch.Tensor, info: torch.Tensor | None = None) -> torch.Tensor:
+        """Factor every matrix of a packed batch in place (one persistent launch)."""
+        nb, pn, po = self._batch_args(n, off)
+        if info is None:
+            info = torch.empty(nb, dtype=torch.int32, device=base.device)
+        self._sync_stream()
+        self._check(self.lib.gpc_factor_batched(self.h, nb, pn, po, _ptr(base), _ptr(info)), "gpc_factor_batched")
+        return info
+
+    def adjoint_batched(self, n, off, Lbase: torch.Tensor, Lbarbase: torch.Tensor) -> torch.Tensor:
+        nb, pn, po = self._batch_args(n, off)
+        self._sync_stream()
+        self._check(self.lib.gpc_adjoint_batched(self.h, nb, pn, po, _ptr(Lbase), _ptr(Lbarbase)),
+                    "gpc_adjoint_batched")
+        return Lbarbase
+
+    def factor_adjoint_batched(self, n, off, base: torch.Tensor, Lbarbase: torch.Tensor,
+                               info: torch.Tensor | None = None) -> torch.Tensor:
+        nb, pn, po = self._batch_args(n, off)
+        if info is None:
+            info = torch.empty(nb, dtype=torch.int32, device=base.device)
+        self._sync_stream()
+        self._check(self.lib.gpc_factor_adjoint_batched(self.h, nb, pn, po, _ptr(base), _ptr(Lbarbase),
+                                                        _ptr(info)), "gpc_factor_adjoint_batched")
+        return info
+
+    def autotune_batched(self, cache_path: str | None = None):
+        self._sync_stream()
+        self._check(self.lib.gpc_autotune_batched(self.h, cache_path.encode() if cache_path else None),
+                    "gpc_autotune_batched")
+
+    def tuning(self):
+        blocks = (_i32 * 5)()
+        tuned = _i32()
+        self._check(self.lib.gpc_get_tuning(self.h, blocks, ctypes.byref(tuned)), "gpc_get_tuning")
+        return list(blocks), bool(tuned.value)
 
     def trace_enable(self, on: bool = True):
         self._check(self.lib.gpc_trace_enable(self.h, 1 if on else 0), "gpc_trace_enable")
