@@ -1,16 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the Cholesky factor + reverse-mode adjoint hot path on one MI355X.
 
+Headline (``value``): FP64, n = 16384 Matern-3/2 covariance on 2-D points
+(x ~ U([0,50]^2), lengthscale 3, noise 0.01 I, Lbar ~ N(0,1), y ~ N(0,1)).
 One step = restore the covariance and the adjoint seed from pristine device
-copies, factor (in place), solve z = L^-1 y and alpha = L^-T z, log-det, then the
-adjoint Abar of the factor.  The workload is the n = 16384 Matern-3/2 covariance
-on 2-D points (x ~ U([0,50]^2), lengthscale 3, noise 0.01 I, Lbar ~ N(0,1)).
-Inputs are generated once on the host, copied to the device before timing and
-stay resident.  value = (n^3/3 + n^2/2 + n/6 + 2 n^3/3) / (seconds per step),
-in GFLOP/s; the solves and copies are inside the timed step but add no flops.
+copies, factor (in place), z = L^-1 y, alpha = L^-T z, log-det, adjoint Abar.
+value = (n^3/3 + n^2/2 + n/6 + 2 n^3/3) / (seconds per step) in GFLOP/s; the
+solves and copies are inside the timed step but add no flops.
 
-Prints ONE JSON line (rank 0).  ``--gpus N`` with N > 1 exits: this build runs
-on one GPU.
+Also measured (under ``config``), each on its own workload:
+  mixed    the same step with FP32-MFMA trailing updates and the FP64 solve
+           replaced by the FP64-refined solve of K alpha = y (eta <= 1e-12),
+           with its error against the FP64 path;
+  batched  512 SE covariances of order U{32..1024} (3-D inputs), factor +
+           adjoint of all in one persistent graph-replayed launch;
+  gp       GP marginal log-likelihood gradient at n = 30000 (SE-ARD, 8-D
+           inputs) through the autograd.Function, FP64 and mixed.
+Inputs are generated on the host with fixed seeds, copied to the device before
+timing and stay resident.  Prints ONE JSON line.  ``--gpus N`` with N > 1
+exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -21,27 +29,41 @@ import sys
 import time
 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense matrix peaks
-PEAK_HBM_GBS = 8000.0
+METRIC = "Cholesky factor+adjoint GFLOP/s @ n=16384, FP64 vs mixed, at stated residual"
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample: int, threads: int | None):
-    """Oracle factor + adjoint on a same-density sample of the workload."""
+def cpu_baseline(n_sample: int):
+    """The oracle's factor + adjoint on a same-density sample of the workload."""
     import oracle
     import workloads as W
     case = W.c3(n=n_sample)
     t0 = time.perf_counter()
-    L, info = oracle.potrf(case["A"])
-    Ab = oracle.potrf_adjoint(L, case["Lbar"])
+    L, _ = oracle.potrf(case["A"])
+    oracle.potrf_adjoint(L, case["Lbar"])
     dt = time.perf_counter() - t0
     F = W.flops_factor(n_sample) + W.flops_adjoint(n_sample)
-    return {"value": F / dt / 1e9, "unit": "GFLOP/s",
-            "cores": threads or os.cpu_count(), "kind": "oracle",
-            "sample": f"factor+adjoint of the same-density Matern-3/2 matrix at n={n_sample} "
-                      f"(1 run, {dt:.1f} s)"}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": round(F / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"factor+adjoint of the same-density Matern-3/2 matrix at n={n_sample}, 1 run, "
+                      f"{dt:.1f} s (GFLOP/s with the same flop count)"}
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
 
 
 def main():
@@ -50,11 +72,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=16384)
-    ap.add_argument("--form", choices=["fp64"], default="fp64")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=5120)
+    ap.add_argument("--gp-evals", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--headline-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
@@ -63,26 +86,25 @@ def main():
     import numpy as np
     import torch
     import workloads as W
-    from paper_1907_01063_amd import Handle
+    from paper_1907_01063_amd import GPC_FP64, GPC_MIXED, Handle, gp_mll
 
     n = args.n
-    log(f"generating workload n={n}")
-    case = W.c3(n=n)
     dev = "cuda"
+    log(f"generating matern32-2d n={n}")
+    case = W.c3(n=n)
     A0 = torch.from_numpy(case["A"]).to(dev)
     Lb0 = torch.from_numpy(case["Lbar"]).to(dev)
     y0 = torch.from_numpy(case["y"]).to(dev)
     del case
-    L = torch.empty_like(A0)
-    Lb = torch.empty_like(Lb0)
-    z = torch.empty_like(y0)
-    a = torch.empty_like(y0)
+    L, Lb = torch.empty_like(A0), torch.empty_like(Lb0)
+    z, a = torch.empty_like(y0), torch.empty_like(y0)
     info = torch.zeros((), dtype=torch.int32, device=dev)
     ld = torch.zeros((), dtype=torch.float64, device=dev)
     H = Handle()
-    H.set_options(block=args.block)
+    H.set_options(block=args.block, precision=GPC_FP64)
+    F = W.flops_factor(n) + W.flops_adjoint(n)
 
-    def step():
+    def step64():
         L.copy_(A0)
         H.factor(L, info)
         z.copy_(y0)
@@ -93,38 +115,22 @@ def main():
         Lb.copy_(Lb0)
         H.adjoint(L, Lb)
 
-    for i in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done")
+    ms = timed(step64, args.steps, args.warmup)
     if int(info.item()) != 0:
         raise SystemExit(f"factor reported info={int(info.item())}")
-
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    log(f"timed {args.steps} steps: {ms:.2f} ms/step")
-    F = W.flops_factor(n) + W.flops_adjoint(n)
     value = F / (ms * 1e-3) / 1e9
-
-    # residuals of the last step (checks, not part of the timing)
+    log(f"fp64: {ms:.2f} ms/step, {value:.0f} GFLOP/s")
     rows = torch.randperm(n, generator=torch.Generator().manual_seed(0))[:64].to(dev)
-    Asym = A0
-    res_fact = (torch.linalg.norm(L[rows] @ L.T - Asym[rows]) / torch.linalg.norm(Asym[rows])).item()
-    r = y0 - Asym @ a
-    eta = (r.abs().max() / (Asym.abs().sum(1).max() * a.abs().max() + y0.abs().max())).item()
-    log(f"sampled ||LL^T-A||/||A|| = {res_fact:.2e}, solve eta_inf = {eta:.2e}")
+    res_fact = (torch.linalg.norm(L[rows] @ L.T - A0[rows]) / torch.linalg.norm(A0[rows])).item()
+    r = y0 - A0 @ a
+    eta64 = (r.abs().max() / (A0.abs().sum(1).max() * a.abs().max() + y0.abs().max())).item()
+    log(f"fp64: sampled |LL^T-A|/|A| = {res_fact:.2e}, direct-solve eta_inf = {eta64:.2e}")
 
     roof = None
     if not args.no_trace:
         H.trace_enable(True)
         H.trace_reset()
-        step()
+        step64()
         tr = H.trace_read()
         H.trace_enable(False)
         mfma = {k: v for k, v in tr.items()
@@ -133,29 +139,122 @@ def main():
         dom = max(mfma, key=lambda k: mfma[k][1])
         cnt, kms, kfl, kby = tr[dom]
         achieved = kfl / (kms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS["f64"]
         roof = {"bound": "mfma", "kernel": dom, "launches": cnt, "achieved": round(achieved, 3),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "avg_launch_ms": round(kms / max(cnt, 1), 4),
-                "classes_ms": {k: round(v[1], 3) for k, v in tr.items()}}
+                "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
+                "traffic": None, "avg_launch_ms": round(kms / max(cnt, 1), 4),
+                "algorithmic_bytes_per_launch": round(kby / max(cnt, 1)),
+                "classes_ms": {k: round(v[1], 3) for k, v in tr.items() if v[0]}}
         log(f"trace: {json.dumps(roof)}")
+
+    cfg = {"workload": f"matern32-2d-n{n} factor+solves+logdet+adjoint", "n": n, "form": "fp64",
+           "block": args.block or 128, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
+           "factor_residual_sampled": res_fact, "solve_eta_inf": eta64}
+
+    if not args.headline_only:
+        # ---- mixed form with the FP64-refined solve
+        Lm, Lbm = torch.empty_like(A0), torch.empty_like(Lb0)
+        xr = torch.empty_like(y0)
+        Hm = Handle()
+        Hm.set_options(block=args.block, precision=GPC_MIXED)
+        out = {}
+
+        def stepmix():
+            Lm.copy_(A0)
+            Hm.factor(Lm, info)
+            out["x"], out["it"], out["eta"] = Hm.solve_refined(A0, Lm, y0, x=xr, check=False)
+            Hm.logdet(Lm, ld)
+            Lbm.copy_(Lb0)
+            Hm.adjoint(Lm, Lbm)
+
+        msm = timed(stepmix, args.steps, args.warmup)
+        it, etam = int(out["it"].item()), float(out["eta"].item())
+        eL = (torch.linalg.norm(Lm - L) / torch.linalg.norm(L)).item()
+        eA = (torch.linalg.norm(Lbm - Lb) / torch.linalg.norm(Lb)).item()
+        ea = (torch.linalg.norm(xr - a) / torch.linalg.norm(a)).item()
+        vm = F / (msm * 1e-3) / 1e9
+        log(f"mixed: {msm:.2f} ms/step, {vm:.0f} GFLOP/s, refine iters {it} eta {etam:.2e}, "
+            f"err vs fp64: L {eL:.2e} Abar {eA:.2e} alpha {ea:.2e}")
+        cfg["mixed"] = {"value": round(vm, 2), "unit": "GFLOP/s", "ms_per_step": round(msm, 3),
+                        "speedup_vs_fp64": round(ms / msm, 3), "refine_iters": it, "refined_eta_inf": etam,
+                        "err_vs_fp64_path": {"L": eL, "Abar": eA, "alpha": ea},
+                        "step": "factor (FP32 trailing updates) + FP64-refined solve + log-det + adjoint"}
+        del Lm, Lbm, Hm
+        del A0, Lb0, L, Lb
+        torch.cuda.empty_cache()
+
+        # ---- batched: 512 uneven matrices, one persistent graph-replayed launch
+        log("generating se3d batch of 512")
+        bc = W.c4()
+        base0 = torch.from_numpy(bc["base"]).to(dev)
+        lbar0 = torch.from_numpy(bc["Lbar"]).to(dev)
+        bw, lw = torch.empty_like(base0), torch.empty_like(lbar0)
+        binfo = torch.zeros(len(bc["n"]), dtype=torch.int32, device=dev)
+        Hb = Handle()
+
+        def stepb():
+            bw.copy_(base0)
+            lw.copy_(lbar0)
+            Hb.factor_adjoint_batched(bc["n"], bc["off"], bw, lw, binfo)
+
+        msb = timed(stepb, args.steps, args.warmup)
+        Fb = float(sum(W.flops_factor(int(k)) + W.flops_adjoint(int(k)) for k in bc["n"]))
+        Hb.trace_enable(True)
+        Hb.trace_reset()
+        stepb()
+        kms_b = Hb.trace_read()["batched"][1]
+        Hb.trace_enable(False)
+        assert int(binfo.max().item()) == 0
+        log(f"batched: {msb:.2f} ms/step (launch {kms_b:.2f} ms), {Fb / (kms_b * 1e-3) / 1e9:.0f} GFLOP/s")
+        cfg["batched"] = {"workload": "se3d-batch512 n~U{32..1024} factor+adjoint", "matrices": len(bc["n"]),
+                          "flops": Fb, "launch_ms": round(kms_b, 3), "ms_per_step_with_copies": round(msb, 3),
+                          "value": round(Fb / (kms_b * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "form": "fp64"}
+        del base0, lbar0, bw, lw, bc, Hb
+        torch.cuda.empty_cache()
+
+        # ---- GP marginal log-likelihood gradient at n = 30000
+        log("generating se-ard 8-d n=30000")
+        gc = W.c5()
+        X = torch.from_numpy(gc["x"]).to(dev)
+        Y = torch.from_numpy(gc["y"]).to(dev)
+        thetas = torch.from_numpy(gc["thetas"]).to(dev)
+        ngp = X.shape[0]
+        Hg = Handle()
+        gp = {}
+        for name, prec in (("fp64", GPC_FP64), ("mixed", GPC_MIXED)):
+            def ev(e=[0]):
+                th = thetas[e[0] % thetas.shape[0]].clone().requires_grad_(True)
+                e[0] += 1
+                f = gp_mll(X, Y, th, precision=prec, handle=Hg, check=False)
+                f.backward()
+                return f, th.grad
+            msg = timed(ev, args.gp_evals, 1)
+            Fg = W.flops_factor(ngp) + W.flops_adjoint(ngp)
+            gp[name] = {"ms_per_eval": round(msg, 2), "gflops_factor_adjoint": round(Fg / (msg * 1e-3) / 1e9, 2)}
+            log(f"gp {name}: {msg:.1f} ms per value+gradient evaluation")
+        th0 = thetas[0].clone().requires_grad_(True)
+        f64v = gp_mll(X, Y, th0, precision=GPC_FP64, handle=Hg)
+        f64v.backward()
+        g64 = th0.grad.clone()
+        th1 = thetas[0].clone().requires_grad_(True)
+        fmv = gp_mll(X, Y, th1, precision=GPC_MIXED, handle=Hg)
+        fmv.backward()
+        gp["mixed"]["err_vs_fp64"] = {"f": abs((fmv - f64v).item()) / abs(f64v.item()),
+                                      "grad": (torch.linalg.norm(th1.grad - g64) / torch.linalg.norm(g64)).item()}
+        gp["speedup_mixed_vs_fp64"] = round(gp["fp64"]["ms_per_eval"] / gp["mixed"]["ms_per_eval"], 3)
+        cfg["gp"] = {"workload": f"se-ard8d-n{ngp} GP marginal log-likelihood + gradient (10 hyperparameters)",
+                     "evals_timed": args.gp_evals, **gp}
+        del X, Y, Hg
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) at n={args.cpu_sample}")
-        cpu = cpu_baseline(args.cpu_sample, int(os.environ.get("OMP_NUM_THREADS", "0")) or None)
+        cpu = cpu_baseline(args.cpu_sample)
 
-    out = {
-        "metric": "Cholesky factor+adjoint GFLOP/s @ n=16384, FP64 vs mixed, at stated residual",
-        "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"matern32-2d-n{n} factor+solves+logdet+adjoint", "n": n,
-                   "form": args.form, "block": args.block or 128,
-                   "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
-                   "factor_residual_sampled": res_fact, "solve_eta_inf": eta},
-        "roofline": roof, "cpu_baseline": cpu,
-    }
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof,
+           "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -42,6 +42,8 @@ struct gpc_handle {
     int tune_block[kTuneBuckets] = {64, 64, 64, 64, 64};
     bool tuned = false;
     hipStream_t cap_stream = nullptr;    // private stream used only to capture graphs
+    hipStream_t side = nullptr;          // second stream of the lookahead schedules
+    std::vector<hipEvent_t> sync_ev;     // ordering events (timing disabled)
     BatchPlan* plan = nullptr;
     hipStream_t stream = nullptr;
     gpc_options opt{};
@@ -58,7 +60,7 @@ namespace {
 
 using namespace gpc;
 
-constexpr int kDefaultBlock = 128;
+constexpr int kDefaultBlock = 256;
 
 gpc_status hip_fail(gpc_handle* h, hipError_t e, const char* what)
 {
@@ -108,7 +110,9 @@ struct Traced {
     gpc_handle* h;
     TraceRec rec{};
     bool on;
-    Traced(gpc_handle* h_, int cls, double flops, double bytes) : h(h_), on(h_->trace)
+    hipStream_t st;
+    Traced(gpc_handle* h_, int cls, double flops, double bytes, hipStream_t s_ = nullptr)
+        : h(h_), on(h_->trace), st(s_ ? s_ : h_->stream)
     {
         if (!on) return;
         rec.cls = cls;
@@ -117,12 +121,12 @@ struct Traced {
         rec.t0 = take_event(h);
         rec.t1 = take_event(h);
         if (!rec.t0 || !rec.t1) { on = false; return; }
-        hipEventRecord(rec.t0, h->stream);
+        hipEventRecord(rec.t0, st);
     }
     ~Traced()
     {
         if (!on) return;
-        hipEventRecord(rec.t1, h->stream);
+        hipEventRecord(rec.t1, st);
         h->recs.push_back(rec);
     }
 };
@@ -162,6 +166,17 @@ void load_tune_cache(gpc_handle* h, const char* path)
             }
     }
     fclose(f);
+}
+
+// i-th ordering event of the current call (grown on demand, reused across calls).
+hipEvent_t sync_event(gpc_handle* h, size_t i)
+{
+    while (h->sync_ev.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        h->sync_ev.push_back(e);
+    }
+    return h->sync_ev[i];
 }
 
 int block_of(const gpc_handle* h) { return h->opt.block > 0 ? h->opt.block : kDefaultBlock; }
@@ -231,7 +246,7 @@ gpc_status gpc_create(gpc_handle** out, void* stream)
     h->stream = (hipStream_t)stream;
     h->opt.precision = GPC_FP64;
     h->opt.block = 0;
-    h->opt.lookahead = 0;
+    h->opt.lookahead = 1;
     h->opt.refine_maxit = 10;
     h->opt.refine_tol = 1e-12;
     h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -249,6 +264,8 @@ gpc_status gpc_destroy(gpc_handle* h)
     for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
     free_plan(h->plan);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    if (h->side) hipStreamDestroy(h->side);
+    for (hipEvent_t e : h->sync_ev) hipEventDestroy(e);
     delete h;
     return st;
 }
@@ -300,7 +317,8 @@ gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
 {
     if (!h || !o) return GPC_ERR_ARG;
     if (o->precision != GPC_FP64 && o->precision != GPC_MIXED) return GPC_ERR_ARG;
-    if (o->block != 0 && o->block != 32 && o->block != 64 && o->block != 128) return GPC_ERR_ARG;
+    if (o->block != 0 && o->block != 32 && o->block != 64 && o->block != 128 && o->block != 256)
+        return GPC_ERR_ARG;
     if (o->refine_maxit < 0 || !(o->refine_tol > 0.0)) return GPC_ERR_ARG;
     h->opt = *o;
     return GPC_OK;
@@ -314,58 +332,145 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* o)
 }
 
 // ---------------------------------------------------------------- factor ---
-// Right-looking blocked factorisation (section 3.3.1) with block b:
-//   for each diagonal block: factor it and form its inverse (one workgroup),
-//   L21 = A21 * inv(L11)^T (MFMA product, in place), A22 -= L21 L21^T on the
-//   lower tiles of the trailing matrix (MFMA SYRK);
-// then the strict upper triangle is zeroed.
+// Right-looking blocked factorisation (section 3.3.1).  Outer block B (256 by
+// default) for the trailing update; within it, 128-wide halves: factor the
+// diagonal block and form its inverse (one workgroup), L21 = A21 inv(L11)^T
+// (MFMA product, in place), and update the next half's columns with the
+// first half's panel.  The trailing update A22 -= P P^T of outer step t is
+// split into the next outer block's columns ("narrow", main stream) and the
+// rest ("big", lower tiles only).  With lookahead the big update of step t
+// runs on a second stream while step t+1's diagonal and panel work proceeds:
+//   main: wait big(t-2); panels(t); record panel(t); wait big(t-1); narrow(t)
+//   side: wait panel(t); big(t); record big(t)
+// (panels(t) touch columns no big(t-1) writes; narrow(t) writes columns
+// big(t-1) writes; FP32 panel copies of the mixed form are double-buffered
+// by step parity, freed by the same waits.)  Then the strict upper triangle
+// is zeroed.
 gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info)
 {
     if (!h || n < 0 || !ld_ok(n, lda) || !info || (n > 0 && !A)) return GPC_ERR_ARG;
     hipStream_t s = h->stream;
     GPC_HIP(h, fill_i32(s, info, 0));
     if (n == 0) return GPC_OK;
-    const int b = block_of(h);
+    const int B = block_of(h);
+    const int ib = std::min(B, kDiagMax);
     const bool mixed = h->opt.precision == GPC_MIXED;
-    // FP64 inverse of the diagonal block; FP32 copy of the panel (mixed)
-    const size_t n_linv = (size_t)b * b;
-    const size_t n_pf = mixed ? (size_t)n * b : 0;
+    const size_t n_linv = (size_t)ib * ib;
+    const size_t n_pf = mixed ? 2 * (size_t)n * B : 0;
     gpc_status st = ensure_ws(h, sizeof(double) * n_linv + sizeof(float) * n_pf);
     if (st != GPC_OK) return st;
     double* Linv = (double*)h->ws;
-    float* Pf = (float*)(Linv + n_linv);
-    for (int64_t k = 0; k < n; k += b) {
-        const int kb = (int)std::min<int64_t>(b, n - k);
-        const double dkb = (double)kb;
-        {
-            Traced t(h, GPC_K_DIAG_FACTOR, dkb * dkb * dkb / 3.0, 16.0 * dkb * dkb);
-            GPC_HIP(h, potrf_diag(s, kb, A + k * lda + k, lda, Linv, b, info, k));
-        }
-        const int64_t m = n - k - kb;
-        if (m <= 0) continue;
-        const double dm = (double)m;
-        double* A21 = A + (k + kb) * lda + k;
-        double* A22 = A + (k + kb) * lda + (k + kb);
-        {
-            Traced t(h, GPC_K_PANEL_SOLVE, dm * dkb * dkb, 8.0 * (2.0 * dm * dkb + dkb * dkb));
-            GemmArgs pg = gemm_args(m, kb, kb, A21, lda, Linv, b, A21, lda);
-            if (mixed) {
-                pg.Cf = Pf;
-                pg.ldcf = b;
+    float* Pf2 = (float*)(Linv + n_linv);
+    const int64_t steps = (n + B - 1) / B;
+    const bool la = h->opt.lookahead != 0 && steps > 2;
+    hipStream_t s2 = s;
+    if (la) {
+        if (!h->side) GPC_HIP(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        s2 = h->side;
+        hipEvent_t e0 = sync_event(h, 0);
+        if (!e0) return GPC_ERR_HIP;
+        GPC_HIP(h, hipEventRecord(e0, s));
+        GPC_HIP(h, hipStreamWaitEvent(s2, e0, 0));
+    }
+    // events: 1 + 2t = panel(t), 2 + 2t = big(t)
+    auto ev_panel = [&](int64_t t) { return sync_event(h, 1 + 2 * (size_t)t); };
+    auto ev_big = [&](int64_t t) { return sync_event(h, 2 + 2 * (size_t)t); };
+    if (la && (!ev_panel(steps) || !ev_big(steps))) return GPC_ERR_HIP;
+
+    for (int64_t t = 0; t < steps; ++t) {
+        const int64_t k = t * B;
+        const int kB = (int)std::min<int64_t>(B, n - k);
+        float* Pf = Pf2 + (t & 1) * (size_t)n * B;   // rows k.. of this step's panel, leading dim B
+        if (la && t >= 2) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(t - 2), 0));
+        for (int h0 = 0; h0 < kB; h0 += ib) {
+            const int64_t kh = k + h0;
+            const int bh = std::min(ib, kB - h0);
+            const double dbh = (double)bh;
+            {
+                Traced tr(h, GPC_K_DIAG_FACTOR, dbh * dbh * dbh / 3.0, 16.0 * dbh * dbh);
+                GPC_HIP(h, potrf_diag(s, bh, A + kh * lda + kh, lda, Linv, ib, info, kh));
             }
-            GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_STORE, false, pg, 1));
+            const int64_t m = n - kh - bh;
+            if (m <= 0) continue;
+            const double dm = (double)m;
+            double* P = A + (kh + bh) * lda + kh;
+            {
+                Traced tr(h, GPC_K_PANEL_SOLVE, dm * dbh * dbh, 8.0 * (2.0 * dm * dbh + dbh * dbh));
+                GemmArgs pg = gemm_args(m, bh, bh, P, lda, Linv, ib, P, lda);
+                if (mixed) {
+                    pg.Cf = Pf + (kh + bh - k) * B + h0;
+                    pg.ldcf = B;
+                }
+                GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_STORE, false, pg, 1));
+            }
+            if (h0 + bh < kB) {   // the next half of this outer block
+                const int nh = std::min(ib, kB - h0 - bh);
+                const double dnh = (double)nh;
+                Traced tr(h, GPC_K_TRAILING_UPDATE, 2.0 * dbh * ((dm - dnh) * dnh + dnh * (dnh + 1.0) / 2.0),
+                          8.0 * (2.0 * dm * dnh + dm * dbh));
+                if (mixed) {
+                    const float* Pr = Pf + (kh + bh - k) * B + h0;
+                    GemmArgs ng = gemm_args(m, nh, bh, Pr, B, Pr, B, P + bh, lda);
+                    ng.c_lower = 1;
+                    GPC_HIP(h, gemm_f32in(s, TILE_128, false, true, EPI_SUB, false, ng, 1));
+                } else {
+                    GemmArgs ng = gemm_args(m, nh, bh, P, lda, P, lda, P + bh, lda);
+                    ng.c_lower = 1;
+                    GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_SUB, false, ng, 1));
+                }
+            }
         }
-        {
-            Traced t(h, GPC_K_TRAILING_UPDATE, dm * (dm + 1.0) * dkb,
-                     (mixed ? 4.0 : 8.0) * dm * dkb + 8.0 * dm * (dm + 1.0));
+        const int64_t m2 = n - k - kB;
+        if (m2 <= 0) break;
+        const int64_t nB = std::min<int64_t>(B, m2), mb = m2 - nB;
+        const double dkB = (double)kB, dnB = (double)nB, dmb = (double)mb;
+        const double* Pd = A + (k + kB) * lda + k;           // panel rows k+kB.., FP64
+        const float* Pr = Pf + (size_t)kB * B;               // same rows, FP32 copy
+        double* Cn = A + (k + kB) * lda + (k + kB);
+        auto big = [&](hipStream_t q) -> gpc_status {
+            if (mb <= 0) return GPC_OK;
+            Traced tr(h, GPC_K_TRAILING_UPDATE, dmb * (dmb + 1.0) * dkB,
+                      (mixed ? 4.0 : 8.0) * dmb * dkB + 8.0 * dmb * (dmb + 1.0), q);
+            double* Cb = Cn + nB * lda + nB;
             if (mixed) {
-                GemmArgs sg = gemm_args(m, m, kb, Pf, b, Pf, b, A22, lda);
-                GPC_HIP(h, gemm_f32in(s, TILE_128, false, true, EPI_SUB, true, sg, 1));
+                GemmArgs bg = gemm_args(mb, mb, kB, Pr + nB * B, B, Pr + nB * B, B, Cb, lda);
+                GPC_HIP(h, gemm_f32in(q, TILE_128, false, true, EPI_SUB, true, bg, 1));
             } else {
-                GemmArgs sg = gemm_args(m, m, kb, A21, lda, A21, lda, A22, lda);
-                GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_SUB, true, sg, 1));
+                GemmArgs bg = gemm_args(mb, mb, kB, Pd + nB * lda, lda, Pd + nB * lda, lda, Cb, lda);
+                GPC_HIP(h, gemm_f64(q, TILE_128, false, true, EPI_SUB, true, bg, 1));
+            }
+            return GPC_OK;
+        };
+        if (la) {
+            GPC_HIP(h, hipEventRecord(ev_panel(t), s));
+            GPC_HIP(h, hipStreamWaitEvent(s2, ev_panel(t), 0));
+            st = big(s2);
+            if (st != GPC_OK) return st;
+            GPC_HIP(h, hipEventRecord(ev_big(t), s2));
+            if (t >= 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(t - 1), 0));
+        }
+        {
+            Traced tr(h, GPC_K_TRAILING_UPDATE, 2.0 * dkB * (dmb * dnB + dnB * (dnB + 1.0) / 2.0),
+                      (mixed ? 4.0 : 8.0) * (double)m2 * dkB + 16.0 * (double)m2 * dnB);
+            if (mixed) {
+                GemmArgs ng = gemm_args(m2, nB, kB, Pr, B, Pr, B, Cn, lda);
+                ng.c_lower = 1;
+                GPC_HIP(h, gemm_f32in(s, TILE_128, false, true, EPI_SUB, false, ng, 1));
+            } else {
+                GemmArgs ng = gemm_args(m2, nB, kB, Pd, lda, Pd, lda, Cn, lda);
+                ng.c_lower = 1;
+                GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_SUB, false, ng, 1));
             }
         }
+        if (!la) {
+            st = big(s);
+            if (st != GPC_OK) return st;
+        }
+    }
+    if (la) {   // join the side stream
+        hipEvent_t ej = sync_event(h, 0);
+        GPC_HIP(h, hipEventRecord(ej, s2));
+        GPC_HIP(h, hipStreamWaitEvent(s, ej, 0));
     }
     GPC_HIP(h, zero_strict_upper(s, n, A, lda));
     return GPC_OK;
@@ -426,7 +531,38 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     {
         const double db = (double)b;
         Traced t(h, GPC_K_DIAG_INVERSE, (double)nblk * db * db * db / 3.0, 8.0 * 2.0 * (double)nblk * db * db);
-        GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+        if (b <= kDiagMax) {
+            GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+        } else {
+            // 256-blocks D = [[D1, 0], [D21, D2]]: D^-1 = [[X1, 0], [-X2 D21 X1, X2]]
+            const int hb = kDiagMax;
+            GPC_HIP(h, fill_f64(s, (int64_t)n_dinv, Dinv, 0.0));
+            GPC_HIP(h, trtri_diag_pairs(s, n, L, ldl, Dinv));
+            double* Tmp = Pd;   // nblk x 128 x 128, free until the sweep
+            GPC_HIP(h, fill_f64(s, nblk * (int64_t)hb * hb, Tmp, 0.0));
+            const int64_t nfull = n / b;
+            auto compose = [&](int64_t p0, int64_t cnt, int64_t m2) -> gpc_status {
+                if (cnt <= 0 || m2 <= 0) return GPC_OK;
+                const double* L21 = L + (p0 * b + hb) * ldl + p0 * b;
+                double* X1 = Dinv + p0 * (int64_t)bb;
+                double* T0 = Tmp + p0 * (int64_t)hb * hb;
+                GemmArgs g1 = gemm_args(m2, hb, hb, L21, ldl, X1, b, T0, hb);
+                g1.bsA = (int64_t)b * ldl + b;
+                g1.bsB = (int64_t)bb;
+                g1.bsC = (int64_t)hb * hb;
+                GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_SUB, false, g1, 1, (int)cnt));
+                GemmArgs g2 = gemm_args(m2, hb, m2, X1 + (int64_t)hb * b + hb, b, T0, hb, X1 + (int64_t)hb * b, b);
+                g2.bsA = (int64_t)bb;
+                g2.bsB = (int64_t)hb * hb;
+                g2.bsC = (int64_t)bb;
+                GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g2, 1, (int)cnt));
+                return GPC_OK;
+            };
+            st = compose(0, nfull, hb);
+            if (st != GPC_OK) return st;
+            st = compose(nfull, nblk - nfull, n - nfull * b - hb);   // ragged last block, if it has a second half
+            if (st != GPC_OK) return st;
+        }
     }
     for (int64_t q = nblk - 1; q >= 0; --q) {
         const int64_t j = q * b, k = std::min<int64_t>(n, j + b), bq = k - j, nr = n - k;
@@ -440,12 +576,24 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         if (nr > 0) {
             {
                 Traced t(h, GPC_K_ADJ_PANEL_SOLVE, dnr * dbq * dbq, 8.0 * (2.0 * dnr * dbq + dbq * dbq));
-                GemmArgs g5 = gemm_args(nr, bq, bq, Cbar, ldlb, Dq_inv, b, Cbar, ldlb);
+                // Cbar <- Cbar D^-1 in place, 128 output columns per launch: the
+                // left columns first (they read the old right ones), then the right.
+                const int64_t hb = std::min<int64_t>(bq, kDiagMax);
+                GemmArgs g5 = gemm_args(nr, hb, bq, Cbar, ldlb, Dq_inv, b, Cbar, ldlb);
                 if (mixed) {
                     g5.Cf = Cf;
                     g5.ldcf = b;
                 }
                 GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g5, 1));
+                if (bq > hb) {
+                    GemmArgs g5b = gemm_args(nr, bq - hb, bq - hb, Cbar + hb, ldlb, Dq_inv + hb * b + hb, b,
+                                             Cbar + hb, ldlb);
+                    if (mixed) {
+                        g5b.Cf = Cf + hb;
+                        g5b.ldcf = b;
+                    }
+                    GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g5b, 1));
+                }
             }
             if (j > 0) {
                 Traced t(h, GPC_K_ADJ_LEFT_UPDATE, 2.0 * dnr * dj * dbq,
@@ -525,10 +673,10 @@ gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const
         return GPC_ERR_ARG;
     if (n == 0 || nrhs == 0) return GPC_OK;
     hipStream_t s = h->stream;
-    const int b = block_of(h);
+    const int b = kDiagMax;   // solves sweep 128-blocks
     const int64_t nblk = (n + b - 1) / b;
     const size_t n_dinv = (size_t)nblk * b * b;
-    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + 8 * (size_t)n));
+    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + (size_t)trsm_workspace(n)));
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
     double* Y = Dinv + n_dinv;
@@ -561,10 +709,10 @@ gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, 
         return GPC_ERR_ARG;
     hipStream_t s = h->stream;
     if (n > 0) {
-        const int b = block_of(h);
+        const int b = kDiagMax;   // solves sweep 128-blocks
         const int64_t nblk = (n + b - 1) / b;
         const size_t n_dinv = (size_t)nblk * b * b;
-        gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + 8 * (size_t)n));
+        gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + (size_t)trsm_workspace(n)));
         if (st != GPC_OK) return st;
         double* Dinv = (double*)h->ws;
         double* Y = Dinv + n_dinv;
@@ -616,15 +764,15 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
         GPC_HIP(h, vec_zero(s, 1, eta));
         return GPC_OK;
     }
-    const int b = block_of(h);
+    const int b = kDiagMax;   // solves sweep 128-blocks
     const int64_t nblk = (n + b - 1) / b;
     const size_t n_dinv = (size_t)nblk * b * b;
     const size_t n_part = (size_t)symv_parts(n);
-    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + 8 * (size_t)n + n_part + 3 * (size_t)n));
+    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + (size_t)trsm_workspace(n) + n_part + 3 * (size_t)n));
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
     double* Y = Dinv + n_dinv;
-    double* part = Y + 8 * (size_t)n;
+    double* part = Y + trsm_workspace(n);
     double* rowabs = part + n_part;
     double* r = rowabs + n;
     double* d = r + n;

@@ -89,7 +89,52 @@ trtri_batched_kernel(int64_t n, int b, const double* L, int64_t ldl, double* Din
     }
 }
 
+__global__ void __launch_bounds__(256)
+trtri_pairs_kernel(int64_t n, const double* L, int64_t ldl, double* Dinv)
+{
+    __shared__ double S[kDiagMax * P];
+    __shared__ double xd[kDiagMax];
+    const int tid = threadIdx.x;
+    const int64_t p = blockIdx.x;
+    const int64_t r0 = p * kDiagMax;
+    const int kb = (int)min((int64_t)kDiagMax, n - r0);
+    const double* D = L + r0 * ldl + r0;
+    double* X = Dinv + (p >> 1) * (2 * kDiagMax) * (2 * kDiagMax) + (p & 1) * (kDiagMax * 2 * kDiagMax + kDiagMax);
+    const int64_t ldx = 2 * kDiagMax;
+    for (int idx = tid; idx < kb * kb; idx += 256) {
+        const int r = idx / kb, c = idx % kb;
+        S[r * P + c] = c <= r ? D[r * ldl + c] : 0.0;
+    }
+    __syncthreads();
+    invert_in_lds(S, xd, kb);
+    for (int idx = tid; idx < kb * kb; idx += 256) {
+        const int r = idx / kb, c = idx % kb;
+        X[r * ldx + c] = c < r ? S[c * P + r] : (c == r ? xd[r] : 0.0);
+    }
+}
+
+__global__ void fill_f64_kernel(int64_t count, double* p, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
 }  // namespace
+
+hipError_t trtri_diag_pairs(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Dinv)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nsub = (n + kDiagMax - 1) / kDiagMax;
+    hipLaunchKernelGGL(trtri_pairs_kernel, dim3((unsigned)nsub), dim3(256), 0, s, n, L, ldl, Dinv);
+    return hipGetLastError();
+}
+
+hipError_t fill_f64(hipStream_t s, int64_t count, double* p, double v)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, p, v);
+    return hipGetLastError();
+}
 
 hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Linv, int64_t ldi,
                       int32_t* info, int64_t col0)

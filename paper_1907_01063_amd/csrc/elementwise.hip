@@ -10,13 +10,20 @@ namespace {
 
 __global__ void fill_i32_kernel(int32_t* p, int32_t v) { *p = v; }
 
-// One thread per element of a 64-wide column strip; blocks that lie entirely
-// on or below the diagonal exit at once.
+// One workgroup per 64 x 64 tile on or above the diagonal (tile index in
+// the row-by-row enumeration of that triangle of tiles); elements with
+// column > row are zeroed.
 __global__ void zero_upper_kernel(int64_t n, double* A, int64_t lda)
 {
-    const int64_t r = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-    if (r < n && c < n && c > r) A[r * lda + c] = 0.0;
+    const int64_t b = blockIdx.x;
+    int64_t t = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while (t * (t + 1) / 2 > b) --t;
+    while ((t + 1) * (t + 2) / 2 <= b) ++t;
+    const int64_t r0 = (b - t * (t + 1) / 2) * 64, c0 = t * 64;   // tile row <= tile column
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int64_t r = r0 + e / 64, c = c0 + e % 64;
+        if (r < n && c < n && c > r) A[r * lda + c] = 0.0;
+    }
 }
 
 __global__ void convert_lower_kernel(int64_t n, const double* L, int64_t ldl, float* Lf, int64_t ldf)
@@ -63,8 +70,8 @@ hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v)
 hipError_t zero_strict_upper(hipStream_t s, int64_t n, double* A, int64_t lda)
 {
     if (n <= 1) return hipSuccess;
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 3) / 4));
-    hipLaunchKernelGGL(zero_upper_kernel, grid, dim3(256), 0, s, n, A, lda);
+    const int64_t t = (n + 63) / 64;
+    hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)(t * (t + 1) / 2)), dim3(256), 0, s, n, A, lda);
     return hipGetLastError();
 }
 

@@ -35,11 +35,19 @@ gemm_kernel(GemmArgs g)
         tm = blockIdx.x / tilesN;
         tn = blockIdx.x % tilesN;
     }
-    gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(g, tm, tn, blockIdx.z, lds);
+    if (blockIdx.y == 0) {
+        gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(g, tm, tn, blockIdx.z, lds);
+    } else {   // member blockIdx.y of a batch of equal-shape products
+        GemmArgs gb = g;
+        gb.A = (const TI*)g.A + blockIdx.y * g.bsA;
+        gb.B = (const TI*)g.B + blockIdx.y * g.bsB;
+        gb.C = g.C + blockIdx.y * g.bsC;
+        gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(gb, tm, tn, blockIdx.z, lds);
+    }
 }
 
 template <typename TI, int BM, int BN, int BK, int WM, int WN, bool AKM, bool BNK, int EPI, bool LOWER>
-hipError_t launch(hipStream_t s, const GemmArgs& g, int splits)
+hipError_t launch(hipStream_t s, const GemmArgs& g, int splits, int batch)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     int64_t tiles;
@@ -49,7 +57,7 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits)
     } else {
         tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     }
-    dim3 grid((unsigned)tiles, 1, (unsigned)(splits < 1 ? 1 : splits));
+    dim3 grid((unsigned)tiles, (unsigned)(batch < 1 ? 1 : batch), (unsigned)(splits < 1 ? 1 : splits));
     hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>), grid, dim3(WM * WN * 64), 0, s, g);
     return hipGetLastError();
 }
@@ -58,11 +66,13 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits)
 
 #define GPC_GEMM_CASE(TI, CFG, BM, BN, BK, AKM, BNK, EPI, LOWER)                                 \
     if (cfg == CFG && a_km == AKM && b_nk == BNK && epi == EPI && lower_tiles == LOWER)           \
-        return launch<TI, BM, BN, BK, (BM == 128 ? 2 : 2), (BM == 128 ? 4 : 2), AKM, BNK, EPI, LOWER>(s, g, splits);
+        return launch<TI, BM, BN, BK, (BM == 128 ? 2 : 2), (BM == 128 ? 4 : 2), AKM, BNK, EPI, LOWER>(s, g, splits, batch);
 
 hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, bool lower_tiles,
-                    const GemmArgs& g, int splits)
+                    const GemmArgs& g, int splits, int batch)
 {
+    // trailing narrow update (C strict upper masked at run time)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_SUB, false)
     // trailing SYRK (lower tiles), panel solve, adjoint panel solve and updates
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_SUB, true)
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_STORE, false)
@@ -78,8 +88,9 @@ hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, b
 }
 
 hipError_t gemm_f32in(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, bool lower_tiles,
-                      const GemmArgs& g, int splits)
+                      const GemmArgs& g, int splits, int batch)
 {
+    GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, true, EPI_SUB, false)
     GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, true, EPI_SUB, true)
     GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, false, EPI_SUB, false)
     GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, true, false, EPI_PARTIAL, false)

@@ -195,7 +195,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                 const int64_t row = m0 + wm * WTM + i * 16 + Mfma<TI>::row(lr, r);
                 const int64_t col = n0 + wn * WTN + j * 16 + lc;
                 if (row >= g.M || col >= g.N) continue;
-                if (LOWER && col > row) continue;
+                if ((LOWER || g.c_lower) && col > row) continue;
                 const double v = (double)acc[i][j][r];
                 if (EPI == EPI_SUB) {
                     g.C[row * g.ldc + col] -= v;

@@ -38,6 +38,8 @@ struct GemmArgs {
     int64_t pstride;    // EPI_PARTIAL slice stride (elements)
     int32_t a_lower;    // nonzero: A is lower-triangular as stored; its strict upper is never read
     float* Cf; int64_t ldcf;  // EPI_STORE / EPI_PHI: optional FP32 copy of the stored C (nullptr = none)
+    int32_t c_lower;          // nonzero: never write C elements with col > row (C-local indices)
+    int64_t bsA, bsB, bsC;    // batch strides (elements) applied per blockIdx.y
 };
 
 enum TileCfg : int { TILE_128 = 0, TILE_64 = 1 };
@@ -45,9 +47,9 @@ enum TileCfg : int { TILE_128 = 0, TILE_64 = 1 };
 // Launchers (hipError_t from the launch).  `lower_tiles`: M == N and only tiles
 // on or below the diagonal are computed, and only elements with m >= n written.
 hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi,
-                    bool lower_tiles, const GemmArgs& g, int splits);
+                    bool lower_tiles, const GemmArgs& g, int splits, int batch = 1);
 hipError_t gemm_f32in(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi,
-                      bool lower_tiles, const GemmArgs& g, int splits);
+                      bool lower_tiles, const GemmArgs& g, int splits, int batch = 1);
 
 // ---- diagonal blocks (single workgroup each) ------------------------------
 // Factor the kb x kb diagonal block at A (in place, upper zeroed), write its
@@ -59,6 +61,11 @@ hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Lin
 // its inverse goes to Dinv + q*b*b (leading dimension b, upper zeroed).
 hipError_t trtri_diag_batched(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl,
                               double* Dinv);
+// Inverses of the 128-blocks of L written into the diagonal quadrants of
+// 256-blocks: sub-block p goes to Dinv + (p/2)*256*256 + (p%2)*(128*256+128),
+// leading dimension 256 (the rest of each 256-block is left untouched).
+hipError_t trtri_diag_pairs(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Dinv);
+hipError_t fill_f64(hipStream_t s, int64_t count, double* p, double v);
 
 // ---- elementwise helpers ---------------------------------------------------
 // Lf[i][j] = (float)L[i][j] for j < i (strict lower triangle only).
@@ -75,7 +82,8 @@ hipError_t reduce_tril(hipStream_t s, int b, const double* D, int64_t ldd, const
 // ---- solves and log-determinant --------------------------------------------
 // B <- L^-1 B (trans 0) or L^-T B (trans 1) by block steps with the diagonal
 // block inverses Dinv (as from trtri_diag_batched, block b).  Y: workspace of
-// 8 * n doubles.
+// trsm_workspace(n) doubles.
+int64_t trsm_workspace(int64_t n);
 hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L,
                         int64_t ldl, const double* Dinv, int b, double* B, int64_t ldb, double* Y);
 // *out = 2 * sum_i log L_ii (fixed summation order).

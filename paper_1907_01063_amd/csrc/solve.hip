@@ -3,13 +3,13 @@
 //
 // The solves sweep the diagonal blocks of L (section 3.2 solves A x = b
 // through the inverse of the triangle; here only the b x b diagonal blocks are
-// inverted, and the off-diagonal blocks are applied as matrix-vector updates).
-// One launch per block step: every workgroup recomputes the step's small
-// product z_q = D_q^-1 y_q (or D_q^-T y_q) from the running right-hand side,
-// workgroup 0 stores it, and each workgroup applies it to its own rows of the
-// remaining right-hand side.  The running right-hand side lives in a separate
-// workspace so that no workgroup reads what another one writes in the step.
-// All are memory-bound matrix-vector work; reductions use fixed shuffle trees.
+// inverted, and the off-diagonal blocks are applied as matrix-vector
+// updates).  One launch per block step q, with lookahead: the step's small
+// product z_q = D_q^-1 y_q (or D_q^-T y_q) was computed by the previous launch,
+// so workgroup 0 of launch q applies z_q to the rows of the next block only and
+// then forms z_{q+1} (double-buffered), while the other workgroups apply z_q to
+// their share of the remaining rows.  The running right-hand side lives in a
+// separate workspace; every reduction has a fixed order.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -18,6 +18,7 @@ namespace gpc {
 namespace {
 
 constexpr int kRhsGroup = 8;   // right-hand sides handled per launch
+constexpr int kRows = 64;      // rows per workgroup of the forward update
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -26,64 +27,170 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Forward step q: rows [j, j+bq) hold y_q in Y; z_q = Dinv_q y_q goes to B
-// (block 0) and Y[r] -= L[r, j:j+bq] z_q for r in [j+bq, n).
-__global__ void __launch_bounds__(256)
-trsv_fwd_step(int64_t n, int nr, int64_t j, int bq, const double* L, int64_t ldl,
-              const double* Dq, int b, double* Y, int64_t ldy, double* B, int64_t ldb,
-              int64_t rows_per_block)
+// rows [r0, r1): Y[r] -= L[r, j:j+bq] z   (z in LDS, bq <= 128), wave per row
+__device__ void fwd_rows(int64_t r0, int64_t r1, int64_t j, int bq, int nr, const double* L, int64_t ldl,
+                         const double (*z)[kRhsGroup], double* Y, int64_t ldy)
 {
-    __shared__ double z[kDiagMax][kRhsGroup];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int i = wave; i < bq; i += 4) {
-        for (int c = 0; c < nr; ++c) {
-            double p = 0.0;
-            for (int t = lane; t <= i; t += 64) p += Dq[(int64_t)i * b + t] * Y[(j + t) * ldy + c];
-            p = wave_sum(p);
-            if (lane == 0) z[i][c] = p;
-        }
-    }
-    __syncthreads();
-    if (blockIdx.x == 0)
-        for (int e = threadIdx.x; e < bq * nr; e += 256) B[(j + e / nr) * ldb + e % nr] = z[e / nr][e % nr];
-    const int64_t r0 = j + bq + (int64_t)blockIdx.x * rows_per_block;
-    const int64_t r1 = min(n, r0 + rows_per_block);
     for (int64_t r = r0 + wave; r < r1; r += 4) {
         const double* lr = L + r * ldl + j;
+        const double l0 = lane < bq ? lr[lane] : 0.0;
+        const double l1 = lane + 64 < bq ? lr[lane + 64] : 0.0;
         for (int c = 0; c < nr; ++c) {
-            double p = 0.0;
-            for (int t = lane; t < bq; t += 64) p += lr[t] * z[t][c];
+            double p = l0 * (lane < bq ? z[lane][c] : 0.0) + l1 * (lane + 64 < bq ? z[lane + 64][c] : 0.0);
             p = wave_sum(p);
             if (lane == 0) Y[r * ldy + c] -= p;
         }
     }
 }
 
-// Backward step q: z_q = Dinv_q^T y_q, then Y[r] -= sum_t L[j+t][r] z_q[t]
-// for r in [0, j).  Threads walk r (contiguous within a row of L).
+// z_out = D^-1 y for the block rows [j, j+bq) of Y; writes z_out and B.
+__device__ void fwd_diag(int64_t j, int bq, int nr, const double* Dq, int b, const double* Y, int64_t ldy,
+                         double (*ys)[kRhsGroup], double* zout, double* B, int64_t ldb)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = threadIdx.x; e < bq * nr; e += 256) ys[e / nr][e % nr] = Y[(j + e / nr) * ldy + e % nr];
+    __syncthreads();
+    for (int i = wave; i < bq; i += 4) {
+        const double d0 = lane <= i ? Dq[(int64_t)i * b + lane] : 0.0;
+        const double d1 = lane + 64 <= i ? Dq[(int64_t)i * b + lane + 64] : 0.0;
+        for (int c = 0; c < nr; ++c) {
+            double p = d0 * (lane < bq ? ys[lane][c] : 0.0) + d1 * (lane + 64 < bq ? ys[lane + 64][c] : 0.0);
+            p = wave_sum(p);
+            if (lane == 0) {
+                zout[i * kRhsGroup + c] = p;
+                B[(j + i) * ldb + c] = p;
+            }
+        }
+    }
+}
+
+// Prologue of the forward sweep: z_0 from the first block.
 __global__ void __launch_bounds__(256)
-trsv_bwd_step(int nr, int64_t j, int bq, const double* L, int64_t ldl, const double* Dq, int b,
-              double* Y, int64_t ldy, double* B, int64_t ldb)
+trsv_fwd_first(int nr, int bq, const double* D0, int b, const double* Y, int64_t ldy, double* zbuf, double* B,
+               int64_t ldb)
+{
+    __shared__ double ys[kDiagMax][kRhsGroup];
+    fwd_diag(0, bq, nr, D0, b, Y, ldy, ys, zbuf, B, ldb);
+}
+
+// Step q of the forward sweep (block rows [j, j+bq), next block [j+bq, j+bq+bq1)).
+__global__ void __launch_bounds__(256)
+trsv_fwd_step(int64_t n, int nr, int64_t j, int bq, int bq1, const double* L, int64_t ldl, const double* Dnext,
+              int b, double* Y, int64_t ldy, const double* zcur, double* znext, double* B, int64_t ldb)
 {
     __shared__ double z[kDiagMax][kRhsGroup];
-    for (int e = threadIdx.x; e < bq * nr; e += 256) {
-        const int i = e / nr, c = e % nr;
-        double p = 0.0;
-        for (int t = i; t < bq; ++t) p += Dq[(int64_t)t * b + i] * Y[(j + t) * ldy + c];
-        z[i][c] = p;
-    }
+    __shared__ double ys[kDiagMax][kRhsGroup];
+    for (int e = threadIdx.x; e < bq * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
     __syncthreads();
-    if (blockIdx.x == 0)
-        for (int e = threadIdx.x; e < bq * nr; e += 256) B[(j + e / nr) * ldb + e % nr] = z[e / nr][e % nr];
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= j) return;
-    double acc[kRhsGroup];
+    const int64_t jn = j + bq;
+    if (blockIdx.x == 0) {
+        fwd_rows(jn, jn + bq1, j, bq, nr, L, ldl, z, Y, ldy);
+        __syncthreads();
+        fwd_diag(jn, bq1, nr, Dnext, b, Y, ldy, ys, znext, B, ldb);
+    } else {
+        const int64_t r0 = jn + bq1 + (int64_t)(blockIdx.x - 1) * kRows;
+        fwd_rows(r0, min(n, r0 + kRows), j, bq, nr, L, ldl, z, Y, ldy);
+    }
+}
+
+// acc[c] = sum_t L[j+t][r] z[t][c] over t in [t0, t1) for one column r.
+__device__ __forceinline__ void bwd_col(int64_t r, int64_t j, int t0, int t1, int nr, const double* L, int64_t ldl,
+                                        const double (*z)[kRhsGroup], double* acc)
+{
     for (int c = 0; c < nr; ++c) acc[c] = 0.0;
-    for (int t = 0; t < bq; ++t) {
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+        const double l0 = L[(j + t) * ldl + r], l1 = L[(j + t + 1) * ldl + r];
+        const double l2 = L[(j + t + 2) * ldl + r], l3 = L[(j + t + 3) * ldl + r];
+        for (int c = 0; c < nr; ++c)
+            acc[c] += ((l0 * z[t][c] + l1 * z[t + 1][c]) + l2 * z[t + 2][c]) + l3 * z[t + 3][c];
+    }
+    for (; t < t1; ++t) {
         const double l = L[(j + t) * ldl + r];
         for (int c = 0; c < nr; ++c) acc[c] += l * z[t][c];
     }
-    for (int c = 0; c < nr; ++c) Y[r * ldy + c] -= acc[c];
+}
+
+// cols [r0, r0+64): Y[r] -= sum_t L[j+t][r] z[t], t split over the 4 waves and
+// combined in wave order.
+__device__ void bwd_cols(int64_t r0, int64_t r1, int64_t j, int bq, int nr, const double* L, int64_t ldl,
+                         const double (*z)[kRhsGroup], double* Y, int64_t ldy, double (*red)[64][kRhsGroup])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r = r0 + lane;
+    const int q4 = (bq + 3) / 4;
+    const int t0 = min(bq, wave * q4), t1 = min(bq, t0 + q4);
+    double acc[kRhsGroup];
+    if (r < r1) bwd_col(r, j, t0, t1, nr, L, ldl, z, acc);
+    else for (int c = 0; c < nr; ++c) acc[c] = 0.0;
+    for (int c = 0; c < nr; ++c) red[wave][lane][c] = acc[c];
+    __syncthreads();
+    if (wave == 0 && r < r1)
+        for (int c = 0; c < nr; ++c)
+            Y[r * ldy + c] -= ((red[0][lane][c] + red[1][lane][c]) + red[2][lane][c]) + red[3][lane][c];
+    __syncthreads();
+}
+
+// z_out = D^-T y for the block [j, j+bq) of Y; writes z_out and B.
+__device__ void bwd_diag(int64_t j, int bq, int nr, const double* Dq, int b, const double* Y, int64_t ldy,
+                         double (*ys)[kRhsGroup], double (*red)[64][kRhsGroup], double* zout, double* B,
+                         int64_t ldb)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = threadIdx.x; e < bq * nr; e += 256) ys[e / nr][e % nr] = Y[(j + e / nr) * ldy + e % nr];
+    __syncthreads();
+    // z[i] = sum_{t >= i} D[t][i] y[t]: columns i over lanes (two halves), t over waves
+    for (int h = 0; h < 2; ++h) {
+        const int i = h * 64 + lane;
+        const int q4 = (bq + 3) / 4;
+        const int t0 = min(bq, wave * q4), t1 = min(bq, t0 + q4);
+        double acc[kRhsGroup];
+        for (int c = 0; c < nr; ++c) acc[c] = 0.0;
+        if (i < bq)
+            for (int t = max(t0, i); t < t1; ++t) {
+                const double d = Dq[(int64_t)t * b + i];
+                for (int c = 0; c < nr; ++c) acc[c] += d * ys[t][c];
+            }
+        for (int c = 0; c < nr; ++c) red[wave][lane][c] = acc[c];
+        __syncthreads();
+        if (wave == 0 && i < bq)
+            for (int c = 0; c < nr; ++c) {
+                const double p = ((red[0][lane][c] + red[1][lane][c]) + red[2][lane][c]) + red[3][lane][c];
+                zout[i * kRhsGroup + c] = p;
+                B[(j + i) * ldb + c] = p;
+            }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256)
+trsv_bwd_first(int nr, int64_t j, int bq, const double* Dq, int b, const double* Y, int64_t ldy, double* zbuf,
+               double* B, int64_t ldb)
+{
+    __shared__ double ys[kDiagMax][kRhsGroup];
+    __shared__ double red[4][64][kRhsGroup];
+    bwd_diag(j, bq, nr, Dq, b, Y, ldy, ys, red, zbuf, B, ldb);
+}
+
+// Step q of the backward sweep: block [j, j+bq) solved (z_q in zcur); the
+// previous block is [jp, j) with jp = j - bqp.
+__global__ void __launch_bounds__(256)
+trsv_bwd_step(int nr, int64_t j, int bq, int64_t jp, int bqp, const double* L, int64_t ldl, const double* Dprev,
+              int b, double* Y, int64_t ldy, const double* zcur, double* znext, double* B, int64_t ldb)
+{
+    __shared__ double z[kDiagMax][kRhsGroup];
+    __shared__ double ys[kDiagMax][kRhsGroup];
+    __shared__ double red[4][64][kRhsGroup];
+    for (int e = threadIdx.x; e < bq * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        for (int64_t r0 = jp; r0 < j; r0 += 64) bwd_cols(r0, min(j, r0 + 64), j, bq, nr, L, ldl, z, Y, ldy, red);
+        bwd_diag(jp, bqp, nr, Dprev, b, Y, ldy, ys, red, znext, B, ldb);
+    } else {
+        const int64_t r0 = (int64_t)(blockIdx.x - 1) * 64;
+        if (r0 < jp) bwd_cols(r0, min(jp, r0 + 64), j, bq, nr, L, ldl, z, Y, ldy, red);
+    }
 }
 
 __global__ void copy_cols(int64_t n, int nr, const double* B, int64_t ldb, double* Y, int64_t ldy)
@@ -110,32 +217,42 @@ __global__ void __launch_bounds__(256) logdet_kernel(int64_t n, const double* L,
 
 }  // namespace
 
+int64_t trsm_workspace(int64_t n) { return (int64_t)kRhsGroup * n + 2 * kDiagMax * kRhsGroup; }
+
 hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
                         const double* Dinv, int b, double* B, int64_t ldb, double* Y)
 {
     const int64_t nblk = (n + b - 1) / b;
+    const int64_t bb = (int64_t)b * b;
+    double* zb = Y + (int64_t)kRhsGroup * n;            // two z slots
+    auto zslot = [&](int64_t q) { return zb + (q & 1) * kDiagMax * kRhsGroup; };
     for (int64_t c0 = 0; c0 < nrhs; c0 += kRhsGroup) {
         const int nr = (int)std::min<int64_t>(kRhsGroup, nrhs - c0);
         double* Bc = B + c0;
         hipLaunchKernelGGL(copy_cols, dim3((unsigned)((n * nr + 255) / 256)), dim3(256), 0, s, n, nr, Bc, ldb, Y,
                            (int64_t)kRhsGroup);
         if (!trans) {
-            for (int64_t q = 0; q < nblk; ++q) {
+            hipLaunchKernelGGL(trsv_fwd_first, dim3(1), dim3(256), 0, s, nr, (int)std::min<int64_t>(b, n), Dinv, b,
+                               Y, (int64_t)kRhsGroup, zslot(0), Bc, ldb);
+            for (int64_t q = 0; q + 1 < nblk; ++q) {
                 const int64_t j = q * b;
-                const int bq = (int)std::min<int64_t>(b, n - j);
-                const int64_t rest = n - j - bq;
-                const int64_t rpb = 64;
-                const int64_t blocks = std::max<int64_t>(1, (rest + rpb - 1) / rpb);
-                hipLaunchKernelGGL(trsv_fwd_step, dim3((unsigned)blocks), dim3(256), 0, s, n, nr, j, bq, L, ldl,
-                                   Dinv + q * (int64_t)b * b, b, Y, (int64_t)kRhsGroup, Bc, ldb, rpb);
+                const int bq = b;
+                const int bq1 = (int)std::min<int64_t>(b, n - j - b);
+                const int64_t rest = n - (j + bq + bq1);
+                const int64_t blocks = 1 + std::max<int64_t>(0, (rest + kRows - 1) / kRows);
+                hipLaunchKernelGGL(trsv_fwd_step, dim3((unsigned)blocks), dim3(256), 0, s, n, nr, j, bq, bq1, L, ldl,
+                                   Dinv + (q + 1) * bb, b, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
             }
         } else {
-            for (int64_t q = nblk - 1; q >= 0; --q) {
-                const int64_t j = q * b;
+            const int64_t jl = (nblk - 1) * b;
+            hipLaunchKernelGGL(trsv_bwd_first, dim3(1), dim3(256), 0, s, nr, jl, (int)(n - jl), Dinv + (nblk - 1) * bb,
+                               b, Y, (int64_t)kRhsGroup, zslot(nblk - 1), Bc, ldb);
+            for (int64_t q = nblk - 1; q >= 1; --q) {
+                const int64_t j = q * b, jp = j - b;
                 const int bq = (int)std::min<int64_t>(b, n - j);
-                const int64_t blocks = std::max<int64_t>(1, (j + 255) / 256);
-                hipLaunchKernelGGL(trsv_bwd_step, dim3((unsigned)blocks), dim3(256), 0, s, nr, j, bq, L, ldl,
-                                   Dinv + q * (int64_t)b * b, b, Y, (int64_t)kRhsGroup, Bc, ldb);
+                const int64_t blocks = 1 + (jp + 63) / 64;
+                hipLaunchKernelGGL(trsv_bwd_step, dim3((unsigned)blocks), dim3(256), 0, s, nr, j, bq, jp, b, L, ldl,
+                                   Dinv + (q - 1) * bb, b, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
             }
         }
         hipError_t e = hipGetLastError();

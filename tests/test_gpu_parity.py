@@ -169,3 +169,36 @@ def test_trsm_vector_and_logdet(H):
     assert relf(host(a), oracle.trsm(Lo, zo, trans=True)) <= TOL
     ld = float(host(H.logdet(Lt)))
     assert abs(ld - oracle.logdet(Lo)) <= TOL * abs(oracle.logdet(Lo))
+
+
+@pytest.mark.parametrize("block,look", [(128, 0), (128, 1), (256, 0), (256, 1)])
+@pytest.mark.parametrize("n", [300, 400, 1100, 1700])
+def test_blocking_and_lookahead_variants(H, block, look, n):
+    # n = 300 / 400: ragged last 256-block with <= 128 / > 128 rows;
+    # 1100 / 1700: several outer steps, so the lookahead schedule is exercised
+    case = W.c3(n=n)
+    say(f"variant block={block} lookahead={look} n={n}")
+    H.set_options(block=block, lookahead=look)
+    try:
+        At = dev(with_upper_garbage(case["A"]))
+        info = H.factor(At)
+        Lbt = dev(with_upper_garbage(case["Lbar"], 5))
+        H.adjoint(At, Lbt)
+        Lg, Ag = host(At), host(Lbt)
+    finally:
+        H.set_options(block=0, lookahead=1)
+    Lo, _ = oracle.potrf(case["A"])
+    Ao = oracle.potrf_adjoint(Lo, case["Lbar"])
+    assert int(host(info)) == 0
+    assert np.all(np.triu(Lg, 1) == 0.0) and np.all(np.triu(Ag, 1) == 0.0)
+    assert relf(Lg, Lo) <= TOL
+    assert relf(Ag, Ao) <= TOL
+
+
+def test_info_with_lookahead(H):
+    # failure in a late outer step while the big updates run on the side stream
+    A = W.c3(n=1300)["A"].copy()
+    A[1100, 1100] = -1.0
+    say("info lookahead")
+    _, info = gpu_factor(H, A)
+    assert info == oracle.potrf(A)[1] == 1101
