@@ -134,20 +134,31 @@ def main():
         tr = H.trace_read()
         H.trace_enable(False)
         mfma = {k: v for k, v in tr.items()
-                if k in ("trailing_update", "adj_left_update", "adj_row_update", "panel_solve",
-                         "adj_panel_solve", "adj_diag_product")}
+                if k in ("trailing_update", "trailing_narrow", "adj_left_update", "adj_row_update",
+                         "panel_solve", "adj_panel_solve", "adj_diag_product")}
         dom = max(mfma, key=lambda k: mfma[k][1])
         cnt, kms, kfl, kby = tr[dom]
         achieved = kfl / (kms * 1e-3) / 1e12
+        # wall clock of each phase of the step (main stream), for the breakdown
+        def phase(fn, reps=2):
+            return round(timed(fn, reps, 0), 3)
+        phases = {"copy_A": phase(lambda: L.copy_(A0)),
+                  "factor": phase(lambda: (L.copy_(A0), H.factor(L, info))) ,
+                  "solves": phase(lambda: (z.copy_(y0), H.trsm(L, z), a.copy_(z), H.trsm(L, a, trans=True))),
+                  "logdet": phase(lambda: H.logdet(L, ld)),
+                  "adjoint": phase(lambda: (Lb.copy_(Lb0), H.adjoint(L, Lb)))}
+        phases["factor"] = round(phases["factor"] - phases["copy_A"], 3)
+        phases["adjoint"] = round(phases["adjoint"] - phases["copy_A"], 3)
+        log(f"phases (ms, copies of the inputs removed): {phases}")
         roof = {"bound": "mfma", "kernel": dom, "launches": cnt, "achieved": round(achieved, 3),
                 "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
                 "traffic": None, "avg_launch_ms": round(kms / max(cnt, 1), 4),
                 "algorithmic_bytes_per_launch": round(kby / max(cnt, 1)),
-                "classes_ms": {k: round(v[1], 3) for k, v in tr.items() if v[0]}}
+                "classes_ms": {k: round(v[1], 3) for k, v in tr.items() if v[0]}, "phases_ms": phases}
         log(f"trace: {json.dumps(roof)}")
 
     cfg = {"workload": f"matern32-2d-n{n} factor+solves+logdet+adjoint", "n": n, "form": "fp64",
-           "block": args.block or 128, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
+           "block": args.block or 256, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
            "factor_residual_sampled": res_fact, "solve_eta_inf": eta64}
 
     if not args.headline_only:
@@ -167,6 +178,11 @@ def main():
             Hm.adjoint(Lm, Lbm)
 
         msm = timed(stepmix, args.steps, args.warmup)
+        cpm = timed(lambda: Lm.copy_(A0), 2, 0)
+        phm = {"factor": round(timed(lambda: (Lm.copy_(A0), Hm.factor(Lm, info)), 2, 0) - cpm, 3),
+               "refined_solve": round(timed(lambda: Hm.solve_refined(A0, Lm, y0, x=xr, check=False), 2, 0), 3),
+               "adjoint": round(timed(lambda: (Lbm.copy_(Lb0), Hm.adjoint(Lm, Lbm)), 2, 0) - cpm, 3)}
+        log(f"mixed phases (ms): {phm}")
         it, etam = int(out["it"].item()), float(out["eta"].item())
         eL = (torch.linalg.norm(Lm - L) / torch.linalg.norm(L)).item()
         eA = (torch.linalg.norm(Lbm - Lb) / torch.linalg.norm(Lb)).item()
@@ -176,6 +192,7 @@ def main():
             f"err vs fp64: L {eL:.2e} Abar {eA:.2e} alpha {ea:.2e}")
         cfg["mixed"] = {"value": round(vm, 2), "unit": "GFLOP/s", "ms_per_step": round(msm, 3),
                         "speedup_vs_fp64": round(ms / msm, 3), "refine_iters": it, "refined_eta_inf": etam,
+                        "phases_ms": phm,
                         "err_vs_fp64_path": {"L": eL, "Abar": eA, "alpha": ea},
                         "step": "factor (FP32 trailing updates) + FP64-refined solve + log-det + adjoint"}
         del Lm, Lbm, Hm

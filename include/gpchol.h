@@ -182,7 +182,7 @@ gpc_status gpc_get_tuning(const gpc_handle* h, int32_t* blocks_out, int32_t* tun
 typedef enum {
     GPC_K_DIAG_FACTOR = 0,      /* diagonal-block factor + inverse (one workgroup) */
     GPC_K_PANEL_SOLVE = 1,      /* L21 = A21 inv(L11)^T */
-    GPC_K_TRAILING_UPDATE = 2,  /* A22 -= L21 L21^T (lower tiles) */
+    GPC_K_TRAILING_UPDATE = 2,  /* A22 -= L21 L21^T (lower tiles, all but the next block's columns) */
     GPC_K_DIAG_INVERSE = 3,     /* inverses of all diagonal blocks (reverse sweep, solves) */
     GPC_K_ADJ_PANEL_SOLVE = 4,  /* Cbar <- Cbar D^-1 */
     GPC_K_ADJ_LEFT_UPDATE = 5,  /* Bbar -= Cbar R */
@@ -191,7 +191,8 @@ typedef enum {
     GPC_K_ADJ_ROW_UPDATE = 8,   /* split-K slices of [M; Cbar]^T [R; B] */
     GPC_K_REDUCE = 9,           /* fixed-order sum of split-K slices into Rbar */
     GPC_K_BATCHED = 10,         /* one persistent batched launch (graph replay) */
-    GPC_K_COUNT = 11
+    GPC_K_TRAILING_NARROW = 11, /* trailing update of the next block's columns only */
+    GPC_K_COUNT = 12
 } gpc_kernel_class;
 
 /* Launch trace, for measurement: while enabled, every launch of the classes

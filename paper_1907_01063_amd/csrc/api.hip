@@ -406,7 +406,7 @@ gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t*
             if (h0 + bh < kB) {   // the next half of this outer block
                 const int nh = std::min(ib, kB - h0 - bh);
                 const double dnh = (double)nh;
-                Traced tr(h, GPC_K_TRAILING_UPDATE, 2.0 * dbh * ((dm - dnh) * dnh + dnh * (dnh + 1.0) / 2.0),
+                Traced tr(h, GPC_K_TRAILING_NARROW, 2.0 * dbh * ((dm - dnh) * dnh + dnh * (dnh + 1.0) / 2.0),
                           8.0 * (2.0 * dm * dnh + dm * dbh));
                 if (mixed) {
                     const float* Pr = Pf + (kh + bh - k) * B + h0;
@@ -450,7 +450,7 @@ gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t*
             if (t >= 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(t - 1), 0));
         }
         {
-            Traced tr(h, GPC_K_TRAILING_UPDATE, 2.0 * dkB * (dmb * dnB + dnB * (dnB + 1.0) / 2.0),
+            Traced tr(h, GPC_K_TRAILING_NARROW, 2.0 * dkB * (dmb * dnB + dnB * (dnB + 1.0) / 2.0),
                       (mixed ? 4.0 : 8.0) * (double)m2 * dkB + 16.0 * (double)m2 * dnB);
             if (mixed) {
                 GemmArgs ng = gemm_args(m2, nB, kB, Pr, B, Pr, B, Cn, lda);

@@ -20,26 +20,51 @@ namespace {
 constexpr int kRhsGroup = 8;   // right-hand sides handled per launch
 constexpr int kRows = 64;      // rows per workgroup of the forward update
 
-__device__ __forceinline__ double wave_sum(double v)
+// Partial dot product of one quarter of a 128-wide row with z (thread quarter
+// q covers columns q, q+4, ..., so the four threads of a row read adjacent
+// words); all loads are independent and issued before any arithmetic.
+__device__ __forceinline__ void quarter_dot(const double* row, int bq, int q, int nr,
+                                            const double (*z)[kRhsGroup], double* acc)
 {
+    double v[32];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    for (int k = 0; k < 32; ++k) {
+        const int c = q + 4 * k;
+        v[k] = c < bq ? row[c] : 0.0;
+    }
+    for (int c = 0; c < nr; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const int cc = q + 4 * k;
+            s += v[k] * (cc < bq ? z[cc][c] : 0.0);
+        }
+        acc[c] = s;
+    }
 }
 
-// rows [r0, r1): Y[r] -= L[r, j:j+bq] z   (z in LDS, bq <= 128), wave per row
+// Combine the four quarter sums of each row (adjacent lanes), fixed order.
+__device__ __forceinline__ double quad_sum(double v)
+{
+    const double a = __shfl_xor(v, 1, 64);      // partner in the pair
+    const double p = (threadIdx.x & 1) ? a + v : v + a;
+    const double b = __shfl_xor(p, 2, 64);
+    return (threadIdx.x & 2) ? b + p : p + b;
+}
+
+// rows [r0, r1): Y[r] -= L[r, j:j+bq] z   (z in LDS, bq <= 128); four threads per row
 __device__ void fwd_rows(int64_t r0, int64_t r1, int64_t j, int bq, int nr, const double* L, int64_t ldl,
                          const double (*z)[kRhsGroup], double* Y, int64_t ldy)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int64_t r = r0 + wave; r < r1; r += 4) {
-        const double* lr = L + r * ldl + j;
-        const double l0 = lane < bq ? lr[lane] : 0.0;
-        const double l1 = lane + 64 < bq ? lr[lane + 64] : 0.0;
+    const int q = threadIdx.x & 3;
+    for (int64_t rb = r0; rb < r1; rb += 64) {
+        const int64_t r = rb + (threadIdx.x >> 2);
+        double acc[kRhsGroup];
+        if (r < r1) quarter_dot(L + r * ldl + j, bq, q, nr, z, acc);
+        else for (int c = 0; c < nr; ++c) acc[c] = 0.0;
         for (int c = 0; c < nr; ++c) {
-            double p = l0 * (lane < bq ? z[lane][c] : 0.0) + l1 * (lane + 64 < bq ? z[lane + 64][c] : 0.0);
-            p = wave_sum(p);
-            if (lane == 0) Y[r * ldy + c] -= p;
+            const double t = quad_sum(acc[c]);
+            if (q == 0 && r < r1) Y[r * ldy + c] -= t;
         }
     }
 }
@@ -48,18 +73,19 @@ __device__ void fwd_rows(int64_t r0, int64_t r1, int64_t j, int bq, int nr, cons
 __device__ void fwd_diag(int64_t j, int bq, int nr, const double* Dq, int b, const double* Y, int64_t ldy,
                          double (*ys)[kRhsGroup], double* zout, double* B, int64_t ldb)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int e = threadIdx.x; e < bq * nr; e += 256) ys[e / nr][e % nr] = Y[(j + e / nr) * ldy + e % nr];
     __syncthreads();
-    for (int i = wave; i < bq; i += 4) {
-        const double d0 = lane <= i ? Dq[(int64_t)i * b + lane] : 0.0;
-        const double d1 = lane + 64 <= i ? Dq[(int64_t)i * b + lane + 64] : 0.0;
+    const int q = threadIdx.x & 3;
+    for (int i0 = 0; i0 < bq; i0 += 64) {
+        const int i = i0 + (threadIdx.x >> 2);
+        double acc[kRhsGroup];
+        if (i < bq) quarter_dot(Dq + (int64_t)i * b, i + 1, q, nr, ys, acc);   // D^-1 is lower
+        else for (int c = 0; c < nr; ++c) acc[c] = 0.0;
         for (int c = 0; c < nr; ++c) {
-            double p = d0 * (lane < bq ? ys[lane][c] : 0.0) + d1 * (lane + 64 < bq ? ys[lane + 64][c] : 0.0);
-            p = wave_sum(p);
-            if (lane == 0) {
-                zout[i * kRhsGroup + c] = p;
-                B[(j + i) * ldb + c] = p;
+            const double t = quad_sum(acc[c]);
+            if (q == 0 && i < bq) {
+                zout[i * kRhsGroup + c] = t;
+                B[(j + i) * ldb + c] = t;
             }
         }
     }
@@ -94,21 +120,19 @@ trsv_fwd_step(int64_t n, int nr, int64_t j, int bq, int bq1, const double* L, in
     }
 }
 
-// acc[c] = sum_t L[j+t][r] z[t][c] over t in [t0, t1) for one column r.
+// acc[c] = sum_t L[j+t][r] z[t][c] over t in [t0, t1) for one column r
+// (t1 - t0 <= 32); the loads are independent and issued together.
 __device__ __forceinline__ void bwd_col(int64_t r, int64_t j, int t0, int t1, int nr, const double* L, int64_t ldl,
                                         const double (*z)[kRhsGroup], double* acc)
 {
-    for (int c = 0; c < nr; ++c) acc[c] = 0.0;
-    int t = t0;
-    for (; t + 4 <= t1; t += 4) {
-        const double l0 = L[(j + t) * ldl + r], l1 = L[(j + t + 1) * ldl + r];
-        const double l2 = L[(j + t + 2) * ldl + r], l3 = L[(j + t + 3) * ldl + r];
-        for (int c = 0; c < nr; ++c)
-            acc[c] += ((l0 * z[t][c] + l1 * z[t + 1][c]) + l2 * z[t + 2][c]) + l3 * z[t + 3][c];
-    }
-    for (; t < t1; ++t) {
-        const double l = L[(j + t) * ldl + r];
-        for (int c = 0; c < nr; ++c) acc[c] += l * z[t][c];
+    double v[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) v[k] = t0 + k < t1 ? L[(j + t0 + k) * ldl + r] : 0.0;
+    for (int c = 0; c < nr; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) s += v[k] * (t0 + k < t1 ? z[t0 + k][c] : 0.0);
+        acc[c] = s;
     }
 }
 
@@ -147,11 +171,20 @@ __device__ void bwd_diag(int64_t j, int bq, int nr, const double* Dq, int b, con
         const int t0 = min(bq, wave * q4), t1 = min(bq, t0 + q4);
         double acc[kRhsGroup];
         for (int c = 0; c < nr; ++c) acc[c] = 0.0;
-        if (i < bq)
-            for (int t = max(t0, i); t < t1; ++t) {
-                const double d = Dq[(int64_t)t * b + i];
-                for (int c = 0; c < nr; ++c) acc[c] += d * ys[t][c];
+        if (i < bq) {
+            double v[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                const int t = t0 + k;
+                v[k] = (t < t1 && t >= i) ? Dq[(int64_t)t * b + i] : 0.0;   // D^-1 is lower
             }
+            for (int c = 0; c < nr; ++c) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int k = 0; k < 32; ++k) sacc += v[k] * (t0 + k < t1 ? ys[t0 + k][c] : 0.0);
+                acc[c] = sacc;
+            }
+        }
         for (int c = 0; c < nr; ++c) red[wave][lane][c] = acc[c];
         __syncthreads();
         if (wave == 0 && i < bq)

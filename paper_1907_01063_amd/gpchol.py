@@ -35,7 +35,7 @@ EXPORTS = (
 # Kernel classes of the launch trace (gpc_kernel_class).
 KERNEL_CLASSES = ("diag_factor", "panel_solve", "trailing_update", "diag_inverse", "adj_panel_solve",
                   "adj_left_update", "adj_diag_product", "adj_diag_block", "adj_row_update", "reduce",
-                  "batched")
+                  "batched", "trailing_narrow")
 
 
 class GpcError(RuntimeError):
