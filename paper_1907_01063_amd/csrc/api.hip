@@ -483,9 +483,21 @@ gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t*
 //   Cbar <- Cbar D^-1;  Bbar -= Cbar R;  Dbar <- tril(Dbar - Cbar^T C);
 //   P = D^T Dbar;  S = tril(P) + stril(P)^T;  M = D^-T S D^-1  (symmetric);
 //   Rbar -= Cbar^T B + M R;  Dbar <- tril(M) - diag(M)/2.
-// The D^-1 of every block come from one batched launch up front; the long
-// products Cbar^T C and Cbar^T B (inner dimension n-k) are split along k into
+// The D^-1 of every block come from launches up front; the long products
+// Cbar^T C and [M; Cbar]^T [R; B] (inner dimension n-j) are split along k into
 // fixed slices that are added in a fixed order.
+//
+// Schedule of step q (block columns [j, k)): the "chain" (panel solve,
+// Cbar^T C, diagonal step) feeds the updates of Bbar and Rbar, which are split
+// into the next block's columns [j-b, j) ("narrow", needed by step q-1's
+// chain) and the rest [0, j-b) ("big").  With lookahead the big updates run on
+// a second stream:
+//   main: wait big(q+2); chain(q); record chain(q); wait big(q+1); narrow(q)
+//   side: wait chain(q); big(q); record big(q)
+// chain(q) reads columns that big(q+1) does not write; narrow(q) writes
+// columns big(q+1) writes.  The FP32 copies of Cbar and M read by big(q) are
+// double-buffered by step parity (chain(q-2), the next writer of the same
+// buffer, waits for big(q)); narrow and big use separate slice buffers.
 gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* Lbar,
                        int64_t ldlb)
 {
@@ -496,24 +508,30 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     const int b = block_of(h);
     const int64_t nblk = (n + b - 1) / b;
     const int kMaxSd = 64, kMaxSr = 32;
-
-    // plan the split counts of every step to size the partial buffers
-    int64_t pr_elems = 1;
-    for (int64_t q = nblk - 1; q >= 0; --q) {
-        const int64_t j = q * b, k = std::min<int64_t>(n, j + b), bq = k - j;
-        if (j == 0) continue;
-        int sr; int64_t ch;
-        splitk_plan(((bq + 127) / 128) * ((j + 127) / 128), bq + (n - k), kMaxSr, &sr, &ch);
-        pr_elems = std::max<int64_t>(pr_elems, (int64_t)sr * bq * j);
-    }
     const bool mixed = h->opt.precision == GPC_MIXED;
+    const bool la = h->opt.lookahead != 0 && nblk > 2;
+    auto tiles128 = [](int64_t M, int64_t N) { return ((M + 127) / 128) * ((N + 127) / 128); };
+
+    // plan the split counts of every step to size the slice buffers
+    int64_t prn_elems = 1, prb_elems = 1;
+    for (int64_t q = nblk - 1; q >= 1; --q) {
+        const int64_t j = q * b, k = std::min<int64_t>(n, j + b), bq = k - j, K = bq + (n - k);
+        const int64_t bn = std::min<int64_t>(b, j), jb = j - bn;
+        int sr; int64_t ch;
+        splitk_plan(tiles128(bq, bn), K, kMaxSr, &sr, &ch);
+        prn_elems = std::max<int64_t>(prn_elems, (int64_t)sr * bq * bn);
+        if (jb > 0) {
+            splitk_plan(tiles128(bq, jb), K, kMaxSr, &sr, &ch);
+            prb_elems = std::max<int64_t>(prb_elems, (int64_t)sr * bq * jb);
+        }
+    }
     const size_t bb = (size_t)b * b;
     const size_t n_dinv = (size_t)nblk * bb, n_pd = (size_t)kMaxSd * bb;
-    const size_t n_dbl = n_dinv + n_pd + 4 * bb + (size_t)pr_elems;
-    // mixed: FP32 copies of the strict lower triangle of L, of the current
-    // Cbar panel and of M (the FP32 operands of the two trailing products)
+    const size_t n_dbl = n_dinv + n_pd + 5 * bb + (size_t)prn_elems + (size_t)prb_elems;
+    // mixed: FP32 copies of the strict lower triangle of L, and (two each) of
+    // the current Cbar panel and of M: the FP32 operands of the updates
     const int64_t ldf = n;
-    const size_t n_flt = mixed ? (size_t)n * n + (size_t)n * b + bb : 0;
+    const size_t n_flt = mixed ? (size_t)n * n + 2 * (size_t)n * b + 2 * bb : 0;
     gpc_status st = ensure_ws(h, sizeof(double) * n_dbl + sizeof(float) * n_flt);
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
@@ -521,11 +539,12 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     double* Wd = Pd + n_pd;
     double* Sw = Wd + bb;
     double* Tw = Sw + bb;
-    double* Mw = Tw + bb;
-    double* Pr = Mw + bb;
-    float* Lf = (float*)(Pr + pr_elems);
-    float* Cf = Lf + (size_t)n * n;
-    float* Mf = Cf + (size_t)n * b;
+    double* Mw2 = Tw + bb;           // two b x b buffers
+    double* Prn = Mw2 + 2 * bb;
+    double* Prb = Prn + prn_elems;
+    float* Lf = (float*)(Prb + prb_elems);
+    float* Cf2 = Lf + (size_t)n * n;
+    float* Mf2 = Cf2 + 2 * (size_t)n * b;
     if (mixed) GPC_HIP(h, convert_lower_f32(s, n, L, ldl, Lf, ldf));
 
     {
@@ -564,6 +583,18 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
             if (st != GPC_OK) return st;
         }
     }
+    hipStream_t s2 = s;
+    if (la) {
+        if (!h->side) GPC_HIP(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        s2 = h->side;
+        hipEvent_t e0 = sync_event(h, 0);
+        if (!e0 || !sync_event(h, 2 + 2 * (size_t)nblk)) return GPC_ERR_HIP;
+        GPC_HIP(h, hipEventRecord(e0, s));
+        GPC_HIP(h, hipStreamWaitEvent(s2, e0, 0));
+    }
+    auto ev_chain = [&](int64_t q) { return sync_event(h, 1 + 2 * (size_t)q); };
+    auto ev_big = [&](int64_t q) { return sync_event(h, 2 + 2 * (size_t)q); };
+
     for (int64_t q = nblk - 1; q >= 0; --q) {
         const int64_t j = q * b, k = std::min<int64_t>(n, j + b), bq = k - j, nr = n - k;
         const double* D = L + j * ldl + j;
@@ -571,8 +602,13 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         double* Dbar = Lbar + j * ldlb + j;
         double* Cbar = Lbar + k * ldlb + j;
         const double* C = L + k * ldl + j;
+        double* Mw = Mw2 + (q & 1) * bb;
+        float* Cf = Cf2 + (q & 1) * (size_t)n * b;
+        float* Mf = Mf2 + (q & 1) * bb;
+        const double dbq = (double)bq, dnr = (double)nr;
+        if (la && q + 2 <= nblk - 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(q + 2), 0));
+        // ---- chain
         int sd = 0;
-        const double dbq = (double)bq, dnr = (double)nr, dj = (double)j;
         if (nr > 0) {
             {
                 Traced t(h, GPC_K_ADJ_PANEL_SOLVE, dnr * dbq * dbq, 8.0 * (2.0 * dnr * dbq + dbq * dbq));
@@ -593,17 +629,6 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
                         g5b.ldcf = b;
                     }
                     GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g5b, 1));
-                }
-            }
-            if (j > 0) {
-                Traced t(h, GPC_K_ADJ_LEFT_UPDATE, 2.0 * dnr * dj * dbq,
-                         16.0 * dnr * dj + (mixed ? 4.0 : 8.0) * (dnr * dbq + dbq * dj));
-                if (mixed) {
-                    GemmArgs g6 = gemm_args(nr, j, bq, Cf, b, Lf + j * ldf, ldf, Lbar + k * ldlb, ldlb);
-                    GPC_HIP(h, gemm_f32in(s, TILE_128, false, false, EPI_SUB, false, g6, 1));
-                } else {
-                    GemmArgs g6 = gemm_args(nr, j, bq, Cbar, ldlb, L + j * ldl, ldl, Lbar + k * ldlb, ldlb);
-                    GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_SUB, false, g6, 1));
                 }
             }
             int64_t ch;
@@ -631,34 +656,73 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
             }
             GPC_HIP(h, gemm_f64(s, TILE_64, true, false, EPI_PHI, false, gm, 1));
         }
-        if (j > 0) {
+        if (j == 0) continue;
+        // ---- updates of Bbar and Rbar, columns [c0, c0 + nc)
+        const int64_t K = bq + nr;
+        auto left = [&](hipStream_t qs, int64_t c0, int64_t nc) -> gpc_status {
+            if (nr <= 0 || nc <= 0) return GPC_OK;
+            const double dnc = (double)nc;
+            Traced t(h, GPC_K_ADJ_LEFT_UPDATE, 2.0 * dnr * dnc * dbq,
+                     16.0 * dnr * dnc + (mixed ? 4.0 : 8.0) * (dnr * dbq + dbq * dnc), qs);
+            if (mixed) {
+                GemmArgs g6 = gemm_args(nr, nc, bq, Cf, b, Lf + j * ldf + c0, ldf, Lbar + k * ldlb + c0, ldlb);
+                GPC_HIP(h, gemm_f32in(qs, TILE_128, false, false, EPI_SUB, false, g6, 1));
+            } else {
+                GemmArgs g6 = gemm_args(nr, nc, bq, Cbar, ldlb, L + j * ldl + c0, ldl, Lbar + k * ldlb + c0, ldlb);
+                GPC_HIP(h, gemm_f64(qs, TILE_128, false, false, EPI_SUB, false, g6, 1));
+            }
+            return GPC_OK;
+        };
+        auto rowupd = [&](hipStream_t qs, int64_t c0, int64_t nc, double* Pbuf) -> gpc_status {
+            if (nc <= 0) return GPC_OK;
+            const double dnc = (double)nc;
             int sr; int64_t ch;
-            const int64_t K = bq + nr;
-            splitk_plan(((bq + 127) / 128) * ((j + 127) / 128), K, kMaxSr, &sr, &ch);
+            splitk_plan(tiles128(bq, nc), K, kMaxSr, &sr, &ch);
             {
-                Traced t(h, GPC_K_ADJ_ROW_UPDATE, 2.0 * dbq * dj * (double)K,
-                         (mixed ? 4.0 : 8.0) * (double)K * (dbq + dj) + 8.0 * sr * dbq * dj);
+                Traced t(h, GPC_K_ADJ_ROW_UPDATE, 2.0 * dbq * dnc * (double)K,
+                         (mixed ? 4.0 : 8.0) * (double)K * (dbq + dnc) + 8.0 * sr * dbq * dnc, qs);
                 if (mixed) {
-                    GemmArgs gr = gemm_args(bq, j, K, Cf, b, Lf + j * ldf, ldf, Pr, j);
+                    GemmArgs gr = gemm_args(bq, nc, K, Cf, b, Lf + j * ldf + c0, ldf, Pbuf, nc);
                     gr.Ahead = Mf;
                     gr.ldah = bq;
                     gr.head_k = bq;
                     gr.kchunk = ch;
-                    gr.pstride = bq * j;
-                    GPC_HIP(h, gemm_f32in(s, TILE_128, true, false, EPI_PARTIAL, false, gr, sr));
+                    gr.pstride = bq * nc;
+                    GPC_HIP(h, gemm_f32in(qs, TILE_128, true, false, EPI_PARTIAL, false, gr, sr));
                 } else {
-                    GemmArgs gr = gemm_args(bq, j, K, Cbar, ldlb, L + j * ldl, ldl, Pr, j);
+                    GemmArgs gr = gemm_args(bq, nc, K, Cbar, ldlb, L + j * ldl + c0, ldl, Pbuf, nc);
                     gr.Ahead = Mw;
                     gr.ldah = bq;
                     gr.head_k = bq;
                     gr.kchunk = ch;
-                    gr.pstride = bq * j;
-                    GPC_HIP(h, gemm_f64(s, TILE_128, true, false, EPI_PARTIAL, false, gr, sr));
+                    gr.pstride = bq * nc;
+                    GPC_HIP(h, gemm_f64(qs, TILE_128, true, false, EPI_PARTIAL, false, gr, sr));
                 }
             }
-            Traced t(h, GPC_K_REDUCE, dbq * dj * sr, 8.0 * (sr + 2.0) * dbq * dj);
-            GPC_HIP(h, reduce_sub(s, bq, j, Pr, sr, bq * j, Lbar + j * ldlb, ldlb));
+            Traced t(h, GPC_K_REDUCE, dbq * dnc * sr, 8.0 * (sr + 2.0) * dbq * dnc, qs);
+            GPC_HIP(h, reduce_sub(qs, bq, nc, Pbuf, sr, bq * nc, Lbar + j * ldlb + c0, ldlb));
+            return GPC_OK;
+        };
+        const int64_t bn = std::min<int64_t>(b, j), jb = j - bn;
+        if (la) {
+            GPC_HIP(h, hipEventRecord(ev_chain(q), s));
+            GPC_HIP(h, hipStreamWaitEvent(s2, ev_chain(q), 0));
+            if ((st = left(s2, 0, jb)) != GPC_OK) return st;
+            if ((st = rowupd(s2, 0, jb, Prb)) != GPC_OK) return st;
+            GPC_HIP(h, hipEventRecord(ev_big(q), s2));
+            if (q + 1 <= nblk - 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(q + 1), 0));
         }
+        if ((st = left(s, jb, bn)) != GPC_OK) return st;
+        if ((st = rowupd(s, jb, bn, Prn)) != GPC_OK) return st;
+        if (!la) {
+            if ((st = left(s, 0, jb)) != GPC_OK) return st;
+            if ((st = rowupd(s, 0, jb, Prb)) != GPC_OK) return st;
+        }
+    }
+    if (la) {   // join the side stream
+        hipEvent_t ej = sync_event(h, 0);
+        GPC_HIP(h, hipEventRecord(ej, s2));
+        GPC_HIP(h, hipStreamWaitEvent(s, ej, 0));
     }
     GPC_HIP(h, zero_strict_upper(s, n, Lbar, ldlb));
     return GPC_OK;

@@ -27,13 +27,18 @@ __global__ void __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_
 gemm_kernel(GemmArgs g)
 {
     __shared__ TI lds[TileLds<TI, BM, BN, BK>::elems];
+    // Workgroups are dealt to the 8 XCDs round-robin (id mod 8).  Renumber so
+    // that XCD x works on the x-th contiguous range of tiles: consecutive
+    // tiles share their row panel, which then stays in that XCD's L2.
+    const int64_t nwg = gridDim.x, w = blockIdx.x, per = nwg / 8;
+    const int64_t t = w < per * 8 ? (w % 8) * per + w / 8 : w;
     int64_t tm, tn;
     if (LOWER) {
-        lower_tile(blockIdx.x, tm, tn);
+        lower_tile(t, tm, tn);
     } else {
         const int64_t tilesN = (g.N + BN - 1) / BN;
-        tm = blockIdx.x / tilesN;
-        tn = blockIdx.x % tilesN;
+        tm = t / tilesN;
+        tn = t % tilesN;
     }
     if (blockIdx.y == 0) {
         gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(g, tm, tn, blockIdx.z, lds);
