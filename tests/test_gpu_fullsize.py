@@ -1,0 +1,130 @@
+"""Parity at the benchmark's full sizes, in the benchmark's launch configuration
+(outer block 256, lookahead on).
+
+n = 4096 (the 4-D SE workload): element-wise against the oracle.
+n = 16384 (the headline Matern-3/2 workload), where the oracle is too slow:
+  outputs the oracle computes on its own (the leading 768 x 768 block of L
+  depends only on the leading block of A), and properties that hold at any
+  size: sampled rows of L L^T - A, the exact closed form Abar(Lbar = L) = I/2,
+  and the GP identity K M = y alpha^T - I for M = Abar + Abar^T (diagonal
+  counted once) with the GP adjoint seed, on sampled columns, in NumPy FP64.
+n = 30000 (the 8-D SE-ARD GP): the hyper-gradient against central finite
+  differences of the log-likelihood value.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from gpu_util import TOL, dev, host, relf, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1907_01063_amd import Handle
+    h = Handle()
+    h.set_options(block=0, lookahead=1)   # the bench's configuration
+    return h
+
+
+def test_n4096_full_parity(H):
+    case = W.c2()
+    say("n=4096 factor+adjoint vs oracle")
+    At = dev(case["A"])
+    info = H.factor(At)
+    Lbt = dev(case["Lbar"])
+    H.adjoint(At, Lbt)
+    Lo, _ = oracle.potrf(case["A"])
+    Ao = oracle.potrf_adjoint(Lo, case["Lbar"])
+    assert int(host(info)) == 0
+    eL, eA = relf(host(At), Lo), relf(host(Lbt), Ao)
+    say(f"  L {eL:.2e}  Abar {eA:.2e}")
+    assert eL <= TOL and eA <= TOL
+
+
+@pytest.fixture(scope="module")
+def c3():
+    say("generating n=16384")
+    return W.c3()
+
+
+def test_n16384_factor_properties(H, c3):
+    A = c3["A"]
+    n = A.shape[0]
+    At = dev(A)
+    info = H.factor(At)
+    L = host(At)
+    del At
+    assert int(host(info)) == 0
+    assert np.all(np.triu(L[:4096, :4096], 1) == 0.0) and np.all(np.triu(L[-2048:, -2048:], 1) == 0.0)
+    m = 768
+    Lo, _ = oracle.potrf(A[:m, :m])
+    e_lead = relf(L[:m, :m], Lo)
+    rows = np.random.default_rng(0).choice(n, size=16, replace=False)
+    R = L[rows] @ L.T - A[rows]
+    e_res = np.linalg.norm(R) / np.linalg.norm(A[rows])
+    say(f"  leading block {e_lead:.2e}, sampled |LL^T - A|/|A| {e_res:.2e}")
+    assert e_lead <= TOL
+    assert e_res <= 1e-13
+
+
+def test_n16384_adjoint_identity(H, c3):
+    At = dev(c3["A"])
+    H.factor(At)
+    Lbt = At.clone()          # Lbar = L gives Abar = I/2 exactly
+    H.adjoint(At, Lbt)
+    n = At.shape[0]
+    Ab = Lbt
+    diag = torch.diagonal(Ab)
+    off = torch.tril(Ab, -1)
+    e_diag = (diag - 0.5).abs().max().item()
+    e_off = off.abs().max().item()
+    say(f"  Abar(L) = I/2: diag err {e_diag:.2e}, off-diag max {e_off:.2e}")
+    assert e_diag <= 1e-11 and e_off <= 1e-11
+    assert torch.count_nonzero(torch.triu(Ab, 1)).item() == 0
+
+
+def test_n16384_gp_adjoint_identity(H, c3):
+    A, y = c3["A"], c3["y"]
+    At = dev(A)
+    H.factor(At)
+    f, z, a, ld = H.gp_value(At, dev(y))
+    Lb = H.gp_lbar(At, a, z)
+    H.adjoint(At, Lb)
+    Ab = host(Lb)
+    alpha = host(a)
+    rng = np.random.default_rng(1)
+    errs = []
+    for c in rng.choice(A.shape[0], size=6, replace=False):
+        col = np.concatenate([Ab[c, :c], [2.0 * Ab[c, c]], Ab[c + 1:, c]])   # M[:, c]
+        lhs = A @ col
+        rhs = y * alpha[c]
+        rhs[c] -= 1.0
+        errs.append(np.linalg.norm(lhs - rhs) / (np.linalg.norm(y) * abs(alpha[c]) + 1.0))
+    say(f"  K M = y alpha^T - I on sampled columns: max rel residual {max(errs):.2e}")
+    assert max(errs) <= 1e-9
+
+
+def test_n30000_gradient_finite_differences(H):
+    from paper_1907_01063_amd import gp_mll
+    case = W.c5(evals=1)
+    X, Y = dev(case["x"]), dev(case["y"])
+    th = case["theta_base"].copy()
+    theta = dev(th).requires_grad_(True)
+    say("n=30000 gradient")
+    f = gp_mll(X, Y, theta, handle=H)
+    f.backward()
+    g = host(theta.grad)
+    for q in (0, 3, 9):
+        hq = 1e-5 * th[q]
+        tp, tm = th.copy(), th.copy()
+        tp[q] += hq
+        tm[q] -= hq
+        fp = float(host(gp_mll(X, Y, dev(tp), handle=H)))
+        fm = float(host(gp_mll(X, Y, dev(tm), handle=H)))
+        fd = (fp - fm) / (2 * hq)
+        say(f"  theta[{q}]: grad {g[q]:.8e}  fd {fd:.8e}")
+        assert abs(fd - g[q]) <= 1e-5 * max(1.0, abs(g[q]))
