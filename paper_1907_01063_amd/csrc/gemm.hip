@@ -30,25 +30,26 @@ gemm_kernel(GemmArgs g)
     // Workgroups are dealt to the 8 XCDs round-robin (id mod 8).  Renumber so
     // that XCD x works on the x-th contiguous range of tiles: consecutive
     // tiles share their row panel, which then stays in that XCD's L2.
-    const int64_t nwg = gridDim.x, w = blockIdx.x, per = nwg / 8;
-    const int64_t t = w < per * 8 ? (w % 8) * per + w / 8 : w;
+    const int nwg = gridDim.x, w = blockIdx.x, per = nwg / 8;
+    const int t = w < per * 8 ? (w % 8) * per + w / 8 : w;
     int64_t tm, tn;
     if (LOWER) {
         lower_tile(t, tm, tn);
     } else {
-        const int64_t tilesN = (g.N + BN - 1) / BN;
+        const int tilesN = (int)((g.N + BN - 1) / BN);
         tm = t / tilesN;
         tn = t % tilesN;
     }
-    if (blockIdx.y == 0) {
-        gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(g, tm, tn, blockIdx.z, lds);
-    } else {   // member blockIdx.y of a batch of equal-shape products
-        GemmArgs gb = g;
-        gb.A = (const TI*)g.A + blockIdx.y * g.bsA;
-        gb.B = (const TI*)g.B + blockIdx.y * g.bsB;
-        gb.C = g.C + blockIdx.y * g.bsC;
-        gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(gb, tm, tn, blockIdx.z, lds);
-    }
+    // tile coordinates are uniform: keep them (and all that derives from
+    // them) in scalar registers
+    tm = __builtin_amdgcn_readfirstlane((int)tm);
+    tn = __builtin_amdgcn_readfirstlane((int)tn);
+    // member blockIdx.y of a batch of equal-shape products (0 when unbatched)
+    GemmArgs gb = g;
+    gb.A = (const TI*)g.A + blockIdx.y * g.bsA;
+    gb.B = (const TI*)g.B + blockIdx.y * g.bsB;
+    gb.C = g.C + blockIdx.y * g.bsC;
+    gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(gb, tm, tn, blockIdx.z, lds);
 }
 
 template <typename TI, int BM, int BN, int BK, int WM, int WN, bool AKM, bool BNK, int EPI, bool LOWER>
@@ -67,6 +68,12 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits, int batch)
     return hipGetLastError();
 }
 
+// The tile loads use 32-bit byte offsets within a 128-row (or k-row) band.
+bool ld_fits(const GemmArgs& g)
+{
+    return g.lda <= (int64_t(1) << 20) && g.ldb <= (int64_t(1) << 20) && g.ldah <= (int64_t(1) << 20);
+}
+
 }  // namespace
 
 #define GPC_GEMM_CASE(TI, CFG, BM, BN, BK, AKM, BNK, EPI, LOWER)                                 \
@@ -76,6 +83,7 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits, int batch)
 hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, bool lower_tiles,
                     const GemmArgs& g, int splits, int batch)
 {
+    if (!ld_fits(g)) return hipErrorInvalidValue;
     // trailing narrow update (C strict upper masked at run time)
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_SUB, false)
     // trailing SYRK (lower tiles), panel solve, adjoint panel solve and updates
@@ -95,6 +103,7 @@ hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, b
 hipError_t gemm_f32in(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, bool lower_tiles,
                       const GemmArgs& g, int splits, int batch)
 {
+    if (!ld_fits(g)) return hipErrorInvalidValue;
     GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, true, EPI_SUB, false)
     GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, true, EPI_SUB, true)
     GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, false, EPI_SUB, false)

@@ -25,6 +25,26 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int lr, int r) { return 4 * lr + r; }
 };
 
+// Operand loads go through buffer resources: a uniform base per chunk plus a
+// thread-constant 32-bit byte offset.  An element outside the operand gets an
+// offset past the resource's range, which the hardware returns as zero, so
+// the loads need no branches and no 64-bit addresses.
+constexpr uint32_t kOffOut = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const void* base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buffer_ld(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ double buffer_ld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ float buffer_ld<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
 // Tile (ti, tj), tj <= ti, of index b in the row-by-row enumeration of the
 // lower triangle of tiles.
 __device__ __forceinline__ void lower_tile(int64_t b, int64_t& ti, int64_t& tj)
@@ -86,57 +106,72 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     const int kA = AKM ? tid / BM : tid % BK;
     const int nB = BNK ? tid / BK : tid % BN;
     const int kB = BNK ? tid % BK : tid / BN;
-    // 32-bit element offsets from the chunk's base pointers (tile-local)
-    int offA[LA], offB[LB];
-    bool vA[LA], vB[LB];
+    // 32-bit byte offsets from the chunk's base pointers (tile-local); rows
+    // (MK/NK) or columns (KM/KN) outside the operand get kOffOut once here
+    uint32_t offA[LA], offB[LB];
 #pragma unroll
     for (int p = 0; p < LA; ++p) {
         const int r = AKM ? kA + p * ASTEP : mA + p * ASTEP;   // stored row within the chunk/tile
         const int c = AKM ? mA : kA;
-        offA[p] = (int)(r * g.lda + c);
-        vA[p] = AKM ? (m0 + mA < g.M) : (m0 + mA + p * ASTEP < g.M);
+        const bool v = AKM ? (m0 + mA < g.M) : (m0 + mA + p * ASTEP < g.M);
+        offA[p] = v ? (uint32_t)(r * g.lda + c) * (uint32_t)sizeof(TI) : kOffOut;
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
         const int r = BNK ? nB + p * BSTEP : kB + p * BSTEP;
         const int c = BNK ? kB : nB;
-        offB[p] = (int)(r * g.ldb + c);
-        vB[p] = BNK ? (n0 + nB + p * BSTEP < g.N) : (n0 + nB < g.N);
+        const bool v = BNK ? (n0 + nB + p * BSTEP < g.N) : (n0 + nB < g.N);
+        offB[p] = v ? (uint32_t)(r * g.ldb + c) * (uint32_t)sizeof(TI) : kOffOut;
     }
 
     TI ra[LA], rb[LB];
 
+    // k-row and lower-mask tests against uniform bounds: per thread only kA,
+    // kB and (mA - kA) live in registers, whatever LA and LB are
+    const int dA = mA - kA;
     auto load = [&](int64_t k0) {
+        const int krem = (int)(kend - k0);          // k rows of this chunk in range
+        const int dmk = (int)(k0 - m0);             // a_lower: element (m, k) masked where m - k > dmk (KM)
+        const bool alow = g.a_lower != 0;
         // A
         if (AKM && k0 < g.head_k) {
-            // chunk touches the head segment: per-element source selection
+            // KM chunk that starts in the head segment: k < head_k reads Ahead
+            // (ld ldah), the rest reads A from its first row
+            const int hrem = (int)(g.head_k - k0);
+            const auto rh = operand_rsrc(Hp + k0 * g.ldah + m0);
+            const auto rm = operand_rsrc(Ap + m0);
 #pragma unroll
             for (int p = 0; p < LA; ++p) {
-                const int64_t gk = k0 + kA + p * ASTEP, gm = m0 + mA;
-                TI v = (TI)0;
-                if (vA[p] && gk < kend) {
-                    const bool up = g.a_lower && gm > gk;
-                    if (!up) v = gk < g.head_k ? Hp[gk * g.ldah + gm] : Ap[(gk - g.head_k) * g.lda + gm];
+                const int kk = kA + p * ASTEP;
+                const bool in = (offA[p] != kOffOut) & (kk < krem) & !(alow & (dA - p * ASTEP > dmk));
+                const uint32_t oh = in & (kk < hrem) ? (uint32_t)(kk * g.ldah + mA) * (uint32_t)sizeof(TI) : kOffOut;
+                if (hrem >= BK) {
+                    ra[p] = buffer_ld<TI>(rh, oh);
+                } else {
+                    const uint32_t om = in & (kk >= hrem) ? (uint32_t)((kk - hrem) * g.lda + mA) * (uint32_t)sizeof(TI) : kOffOut;
+                    ra[p] = buffer_ld<TI>(rh, oh) + buffer_ld<TI>(rm, om);   // one of the two is zero
                 }
-                ra[p] = v;
             }
         } else {
-            const TI* base = AKM ? Ap + (k0 - g.head_k) * g.lda + m0 : Ap + m0 * g.lda + k0;
+            // offsets selected first, then all loads issued back to back
+            uint32_t o[LA];
 #pragma unroll
             for (int p = 0; p < LA; ++p) {
-                const int64_t gk = AKM ? k0 + kA + p * ASTEP : k0 + kA;
-                const int64_t gm = AKM ? m0 + mA : m0 + mA + p * ASTEP;
-                const bool ok = vA[p] && gk < kend && !(g.a_lower && (AKM ? gm > gk : gk > gm));
-                ra[p] = ok ? base[offA[p]] : (TI)0;
+                const bool ok = AKM ? (kA < krem - p * ASTEP) & !(alow & (dA > dmk + p * ASTEP))
+                                    : (kA < krem) & !(alow & (-dA > p * ASTEP - dmk));
+                o[p] = ok ? offA[p] : kOffOut;
             }
+            const auto rs = operand_rsrc(AKM ? Ap + (k0 - g.head_k) * g.lda + m0 : Ap + m0 * g.lda + k0);
+#pragma unroll
+            for (int p = 0; p < LA; ++p) ra[p] = buffer_ld<TI>(rs, o[p]);
         }
         // B
-        const TI* bbase = BNK ? Bp + n0 * g.ldb + k0 : Bp + k0 * g.ldb + n0;
+        uint32_t o[LB];
 #pragma unroll
-        for (int p = 0; p < LB; ++p) {
-            const int64_t gk = BNK ? k0 + kB : k0 + kB + p * BSTEP;
-            rb[p] = (vB[p] && gk < kend) ? bbase[offB[p]] : (TI)0;
-        }
+        for (int p = 0; p < LB; ++p) o[p] = (BNK ? kB < krem : kB < krem - p * BSTEP) ? offB[p] : kOffOut;
+        const auto rs = operand_rsrc(BNK ? Bp + n0 * g.ldb + k0 : Bp + k0 * g.ldb + n0);
+#pragma unroll
+        for (int p = 0; p < LB; ++p) rb[p] = buffer_ld<TI>(rs, o[p]);
     };
     auto store = [&](int buf) {
 #pragma unroll
