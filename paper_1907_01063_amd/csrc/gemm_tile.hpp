@@ -139,18 +139,29 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
             // (ld ldah), the rest reads A from its first row
             const int hrem = (int)(g.head_k - k0);
             const auto rh = operand_rsrc(Hp + k0 * g.ldah + m0);
-            const auto rm = operand_rsrc(Ap + m0);
+            uint32_t oh[LA];
+            bool in[LA];
 #pragma unroll
             for (int p = 0; p < LA; ++p) {
                 const int kk = kA + p * ASTEP;
-                const bool in = (offA[p] != kOffOut) & (kk < krem) & !(alow & (dA - p * ASTEP > dmk));
-                const uint32_t oh = in & (kk < hrem) ? (uint32_t)(kk * g.ldah + mA) * (uint32_t)sizeof(TI) : kOffOut;
-                if (hrem >= BK) {
-                    ra[p] = buffer_ld<TI>(rh, oh);
-                } else {
-                    const uint32_t om = in & (kk >= hrem) ? (uint32_t)((kk - hrem) * g.lda + mA) * (uint32_t)sizeof(TI) : kOffOut;
-                    ra[p] = buffer_ld<TI>(rh, oh) + buffer_ld<TI>(rm, om);   // one of the two is zero
+                in[p] = (offA[p] != kOffOut) & (kk < krem) & !(alow & (dA - p * ASTEP > dmk));
+                oh[p] = in[p] & (kk < hrem) ? (uint32_t)(kk * g.ldah + mA) * (uint32_t)sizeof(TI) : kOffOut;
+            }
+            if (hrem >= BK) {            // whole chunk in the head
+#pragma unroll
+                for (int p = 0; p < LA; ++p) ra[p] = buffer_ld<TI>(rh, oh[p]);
+            } else {                     // chunk straddles the end of the head
+                const auto rm = operand_rsrc(Ap + m0);
+                TI h[LA];
+#pragma unroll
+                for (int p = 0; p < LA; ++p) {
+                    const int kk = kA + p * ASTEP;
+                    const uint32_t om = in[p] & (kk >= hrem) ? (uint32_t)((kk - hrem) * g.lda + mA) * (uint32_t)sizeof(TI) : kOffOut;
+                    h[p] = buffer_ld<TI>(rh, oh[p]);
+                    ra[p] = buffer_ld<TI>(rm, om);
                 }
+#pragma unroll
+                for (int p = 0; p < LA; ++p) ra[p] += h[p];   // one of the two is zero
             }
         } else {
             // offsets selected first, then all loads issued back to back
@@ -195,29 +206,38 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
 
     const int lr = lane >> 4, lc = lane & 15;
     const int64_t nchunk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+    auto compute = [&](int cur) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            TI a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[i] = sA(cur, kk + lr)[wm * WTM + i * 16 + lc];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = sB(cur, kk + lr)[wn * WTN + j * 16 + lc];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = Mfma<TI>::op(a[i], b[j], acc[i][j]);
+        }
+    };
     if (nchunk > 0) {
         load(kbeg);
         store(0);
         __syncthreads();
-        for (int64_t c = 0; c < nchunk; ++c) {
+        // the last chunk is peeled off, so every iteration's loads are
+        // consumed by its own LDS stores (no load is ever pending across the
+        // back edge, and the loads of one chunk are issued back to back)
+        int64_t c = 0;
+        for (; c + 1 < nchunk; ++c) {
             const int cur = (int)(c & 1);
-            if (c + 1 < nchunk) load(kbeg + (c + 1) * BK);
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                TI a[FM], b[FN];
-#pragma unroll
-                for (int i = 0; i < FM; ++i) a[i] = sA(cur, kk + lr)[wm * WTM + i * 16 + lc];
-#pragma unroll
-                for (int j = 0; j < FN; ++j) b[j] = sB(cur, kk + lr)[wn * WTN + j * 16 + lc];
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[i][j] = Mfma<TI>::op(a[i], b[j], acc[i][j]);
-            }
-            if (c + 1 < nchunk) store(cur ^ 1);
+            load(kbeg + (c + 1) * BK);
+            compute(cur);
+            store(cur ^ 1);
             __syncthreads();
         }
+        compute((int)(c & 1));
+        __syncthreads();
     }
 
     // epilogue
