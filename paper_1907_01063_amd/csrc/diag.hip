@@ -63,8 +63,8 @@ __device__ void invert_in_lds(double* S, double* xd, int kb)
 __global__ void __launch_bounds__(256)
 potrf_diag_kernel(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info, int64_t col0)
 {
-    __shared__ double colbuf[kDiagMax], rowbuf[kDiagMax], sljj;
-    diag_factor_inverse<kDiagMax / 16>(kb, A, lda, Linv, ldi, info, col0, colbuf, rowbuf, &sljj);
+    __shared__ double colbuf[2 * kDiagMax], rowbuf[2 * kDiagMax], piv[4], rls[kDiagMax];
+    diag_factor_inverse<kDiagMax / 16>(kb, A, lda, Linv, ldi, info, col0, colbuf, rowbuf, piv, rls);
 }
 
 __global__ void __launch_bounds__(256)
@@ -140,7 +140,7 @@ hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Lin
                       int32_t* info, int64_t col0)
 {
     if (kb <= 0) return hipSuccess;
-    if (kb > kDiagMax) return hipErrorInvalidValue;
+    if (kb > kDiagMax || lda > (int64_t(1) << 20)) return hipErrorInvalidValue;   // 31-bit row-band offsets
     hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
     return hipGetLastError();
 }
