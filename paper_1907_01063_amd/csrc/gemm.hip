@@ -68,10 +68,12 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits, int batch)
     return hipGetLastError();
 }
 
-// The tile loads use 32-bit byte offsets within a 128-row (or k-row) band.
+// The tile loads (operands, and C for the subtracting products) use 32-bit
+// byte offsets within a 128-row (or k-row) band.
 bool ld_fits(const GemmArgs& g)
 {
-    return g.lda <= (int64_t(1) << 20) && g.ldb <= (int64_t(1) << 20) && g.ldah <= (int64_t(1) << 20);
+    return g.lda <= (int64_t(1) << 20) && g.ldb <= (int64_t(1) << 20) && g.ldah <= (int64_t(1) << 20) &&
+           g.ldc <= (int64_t(1) << 20);
 }
 
 }  // namespace

@@ -12,6 +12,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
     typedef d4v acc_t;
+    typedef double elem_t;
     static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -19,6 +20,7 @@ template <> struct Mfma<double> {
 };
 template <> struct Mfma<float> {
     typedef f4v acc_t;
+    typedef float elem_t;
     static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -77,7 +79,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     constexpr int ASTEP = AKM ? NT / BM : NT / BK;
     constexpr int BSTEP = BNK ? NT / BK : NT / BN;
     static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile/thread mismatch");
-    typedef typename Mfma<TI>::acc_t acc_t;
 
     typedef TI RowA[BM + PAD];
     typedef TI RowB[BN + PAD];
@@ -184,11 +185,37 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
 #pragma unroll
         for (int p = 0; p < LB; ++p) rb[p] = buffer_ld<TI>(rs, o[p]);
     };
+    // FP64 subtract: the accumulators start at C and the MFMAs are fed -A,
+    // so they form C - A B directly and the epilogue only writes.  The C
+    // loads are issued right after the first operand chunk's, so their
+    // latency overlaps it instead of following the last MFMA.
+    constexpr bool kFold = EPI == EPI_SUB && sizeof(TI) == 8;
+    typedef typename Mfma<TI>::acc_t acc_t;
+    acc_t acc[FM][FN];
+    const int lr = lane >> 4, lc = lane & 15;
+    auto load_c = [&]() {
+        const auto rc = operand_rsrc(g.C + m0 * g.ldc + n0);
+        const uint32_t ldc8 = (uint32_t)g.ldc * 8u;
+        const bool lowc = LOWER || g.c_lower;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm * WTM + i * 16 + Mfma<TI>::row(lr, r);
+                    const int col = wn * WTN + j * 16 + lc;
+                    const bool in = (m0 + row < g.M) & (n0 + col < g.N) & !(lowc & (n0 + col > m0 + row));
+                    acc[i][j][r] = (typename Mfma<TI>::elem_t)buffer_ld<double>(
+                        rc, in ? (uint32_t)row * ldc8 + (uint32_t)col * 8u : kOffOut);
+                }
+    };
     auto store = [&](int buf) {
 #pragma unroll
         for (int p = 0; p < LA; ++p) {
-            if (AKM) sA(buf, kA + p * ASTEP)[mA] = ra[p];
-            else sA(buf, kA)[mA + p * ASTEP] = ra[p];
+            const TI v = kFold ? -ra[p] : ra[p];
+            if (AKM) sA(buf, kA + p * ASTEP)[mA] = v;
+            else sA(buf, kA)[mA + p * ASTEP] = v;
         }
 #pragma unroll
         for (int p = 0; p < LB; ++p) {
@@ -197,14 +224,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
         }
     };
 
-    acc_t acc[FM][FN];
+    if (!kFold) {
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-            acc[i][j] = acc_t{0, 0, 0, 0};
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = acc_t{0, 0, 0, 0};
+    }
 
-    const int lr = lane >> 4, lc = lane & 15;
     const int64_t nchunk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
     auto compute = [&](int cur) {
 #pragma unroll
@@ -223,6 +250,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     };
     if (nchunk > 0) {
         load(kbeg);
+        if (kFold) load_c();
         store(0);
         __syncthreads();
         // the last chunk is peeled off, so every iteration's loads are
@@ -238,6 +266,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
         }
         compute((int)(c & 1));
         __syncthreads();
+    } else if (kFold) {
+        load_c();
     }
 
     // epilogue
@@ -253,7 +283,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                 if ((LOWER || g.c_lower) && col > row) continue;
                 const double v = (double)acc[i][j][r];
                 if (EPI == EPI_SUB) {
-                    g.C[row * g.ldc + col] -= v;
+                    if (kFold) g.C[row * g.ldc + col] = v;
+                    else g.C[row * g.ldc + col] -= v;
                 } else if (EPI == EPI_STORE) {
                     g.C[row * g.ldc + col] = v;
                     if (g.Cf) g.Cf[row * g.ldcf + col] = (float)v;
