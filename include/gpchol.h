@@ -59,6 +59,10 @@ typedef struct {
     int32_t lookahead;     /* 1 = overlap the next diagonal step with the trailing update */
     int32_t refine_maxit;  /* maximum refinement iterations of gpc_solve_refined (default 10) */
     double  refine_tol;    /* stop when the normwise backward error eta_inf <= refine_tol (default 1e-12) */
+    int32_t mixed_fallback; /* GPC_MIXED factor: 1 (default) = keep a copy of A and, if the
+                               FP32-updated Schur complement loses definiteness (info != 0),
+                               factor again in FP64 from the copy (see gpc_get_fallback) */
+    int32_t reserved;      /* 0 */
 } gpc_options;
 
 typedef struct gpc_handle gpc_handle;
@@ -76,7 +80,8 @@ gpc_status gpc_destroy(gpc_handle* h);
 gpc_status gpc_set_stream(gpc_handle* h, void* hip_stream);
 
 /* Replace the handle's options (copied).  GPC_ERR_ARG on NULL, an unknown
- * precision, block not in {0, 64, 128, 256}, refine_maxit < 0 or refine_tol <= 0. */
+ * precision, block not in {0, 32, 64, 128, 256}, refine_maxit < 0 or
+ * refine_tol <= 0. */
 gpc_status gpc_set_options(gpc_handle* h, const gpc_options* opt);
 gpc_status gpc_get_options(const gpc_handle* h, gpc_options* opt);
 
@@ -85,8 +90,17 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* opt);
  * the lower triangle of A holds L and its strict upper triangle holds 0.
  * info_dev (device int32) receives 0, or j+1 for the first column j whose pivot
  * is not positive or is NaN; L is then unspecified.
- * Uses the handle's precision (GPC_MIXED: trailing updates in FP32). */
+ * Uses the handle's precision (GPC_MIXED: trailing updates in FP32).
+ * GPC_MIXED with mixed_fallback set: A is first copied to a handle-owned
+ * buffer (n x n doubles, grow-only), the call waits for the stream once to
+ * read info, and on a failed pivot restores A and factors it again in FP64;
+ * info then reports the FP64 result (so a matrix that is not SPD in FP64
+ * still gets its failing column).  Such a call cannot be graph-captured. */
 gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info_dev);
+
+/* *fell_back = 1 if the last gpc_factor on this handle was a GPC_MIXED call
+ * whose FP32-updated factor failed and was redone in FP64, else 0. */
+gpc_status gpc_get_fallback(const gpc_handle* h, int32_t* fell_back);
 
 /* Reverse-mode derivative of the factor (section 3.3.2: the blocked gradient
  * with the diagonal of each diagonal block's adjoint halved and its upper

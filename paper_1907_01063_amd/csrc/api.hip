@@ -49,6 +49,9 @@ struct gpc_handle {
     gpc_options opt{};
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    double* acopy = nullptr;             // copy of A for the mixed factor's FP64 fallback
+    size_t acopy_bytes = 0;
+    int32_t fell_back = 0;
     char err[256] = {0};
     bool trace = false;
     std::vector<TraceRec> recs;        // launches recorded since the last reset
@@ -249,6 +252,7 @@ gpc_status gpc_create(gpc_handle** out, void* stream)
     h->opt.lookahead = 1;
     h->opt.refine_maxit = 10;
     h->opt.refine_tol = 1e-12;
+    h->opt.mixed_fallback = 1;
     h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     load_tune_cache(h, getenv("GPC_TUNE_CACHE"));
     *out = h;
@@ -261,6 +265,7 @@ gpc_status gpc_destroy(gpc_handle* h)
     gpc_status st = GPC_OK;
     if (hipStreamSynchronize(h->stream) != hipSuccess) st = GPC_ERR_HIP;
     if (h->ws && hipFree(h->ws) != hipSuccess) st = GPC_ERR_HIP;
+    if (h->acopy && hipFree(h->acopy) != hipSuccess) st = GPC_ERR_HIP;
     for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
     free_plan(h->plan);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
@@ -320,6 +325,7 @@ gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
     if (o->block != 0 && o->block != 32 && o->block != 64 && o->block != 128 && o->block != 256)
         return GPC_ERR_ARG;
     if (o->refine_maxit < 0 || !(o->refine_tol > 0.0)) return GPC_ERR_ARG;
+    if (o->mixed_fallback != 0 && o->mixed_fallback != 1) return GPC_ERR_ARG;
     h->opt = *o;
     return GPC_OK;
 }
@@ -346,15 +352,15 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* o)
 // big(t-1) writes; FP32 panel copies of the mixed form are double-buffered
 // by step parity, freed by the same waits.)  Then the strict upper triangle
 // is zeroed.
-gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info)
+namespace {
+
+gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info, bool mixed)
 {
-    if (!h || n < 0 || !ld_ok(n, lda) || !info || (n > 0 && !A)) return GPC_ERR_ARG;
     hipStream_t s = h->stream;
     GPC_HIP(h, fill_i32(s, info, 0));
     if (n == 0) return GPC_OK;
     const int B = block_of(h);
     const int ib = std::min(B, kDiagMax);
-    const bool mixed = h->opt.precision == GPC_MIXED;
     const size_t n_linv = (size_t)ib * ib;
     const size_t n_pf = mixed ? 2 * (size_t)n * B : 0;
     gpc_status st = ensure_ws(h, sizeof(double) * n_linv + sizeof(float) * n_pf);
@@ -473,6 +479,52 @@ gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t*
         GPC_HIP(h, hipStreamWaitEvent(s, ej, 0));
     }
     GPC_HIP(h, zero_strict_upper(s, n, A, lda));
+    return GPC_OK;
+}
+
+}  // namespace
+
+gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info)
+{
+    if (!h || n < 0 || !ld_ok(n, lda) || !info || (n > 0 && !A)) return GPC_ERR_ARG;
+    h->fell_back = 0;
+    const bool mixed = h->opt.precision == GPC_MIXED;
+    if (!mixed || !h->opt.mixed_fallback || n == 0) return factor_impl(h, n, A, lda, info, mixed);
+    hipStream_t s = h->stream;
+    const size_t bytes = sizeof(double) * (size_t)n * (size_t)n;
+    if (bytes > h->acopy_bytes) {
+        if (h->acopy) {
+            GPC_HIP(h, hipStreamSynchronize(s));
+            GPC_HIP(h, hipFree(h->acopy));
+            h->acopy = nullptr;
+            h->acopy_bytes = 0;
+        }
+        const hipError_t e = hipMalloc((void**)&h->acopy, bytes);
+        if (e != hipSuccess) {
+            snprintf(h->err, sizeof(h->err), "copy of A, %zu bytes: %s", bytes, hipGetErrorString(e));
+            h->acopy = nullptr;
+            return GPC_ERR_ALLOC;
+        }
+        h->acopy_bytes = bytes;
+    }
+    const size_t row = sizeof(double) * (size_t)n;
+    GPC_HIP(h, hipMemcpy2DAsync(h->acopy, row, A, sizeof(double) * lda, row, n, hipMemcpyDeviceToDevice, s));
+    gpc_status st = factor_impl(h, n, A, lda, info, true);
+    if (st != GPC_OK) return st;
+    int32_t info_h = 0;
+    GPC_HIP(h, hipMemcpyAsync(&info_h, info, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GPC_HIP(h, hipStreamSynchronize(s));
+    if (info_h == 0) return GPC_OK;
+    // the FP32 trailing updates lost definiteness: start again in FP64
+    GPC_HIP(h, hipMemcpy2DAsync(A, sizeof(double) * lda, h->acopy, row, row, n, hipMemcpyDeviceToDevice, s));
+    h->fell_back = 1;
+    return factor_impl(h, n, A, lda, info, false);
+}
+
+gpc_status gpc_get_fallback(const gpc_handle* h, int32_t* fell_back)
+{
+    if (!h || !fell_back) return GPC_ERR_ARG;
+    *fell_back = h->fell_back;
     return GPC_OK;
 }
 

@@ -24,7 +24,7 @@ GPC_NOTRANS, GPC_TRANS = 0, 1
 # Every symbol the header declares, in declaration order.
 EXPORTS = (
     "gpc_create", "gpc_destroy", "gpc_set_stream", "gpc_set_options", "gpc_get_options",
-    "gpc_factor", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
+    "gpc_factor", "gpc_get_fallback", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
     "gpc_solve_refined", "gpc_gp_kgen_se", "gpc_gp_value", "gpc_gp_lbar", "gpc_gp_hypergrad_se",
     "gpc_factor_batched", "gpc_adjoint_batched", "gpc_factor_adjoint_batched", "gpc_autotune_batched",
     "gpc_get_tuning",
@@ -47,7 +47,8 @@ class GpcError(RuntimeError):
 class gpc_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("lookahead", ctypes.c_int32), ("refine_maxit", ctypes.c_int32),
-                ("refine_tol", ctypes.c_double)]
+                ("refine_tol", ctypes.c_double), ("mixed_fallback", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _i64, _i32, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
@@ -82,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "gpc_factor_adjoint_batched": [_vp, _i32, _vp, _vp, _vp, _vp, _vp],
         "gpc_autotune_batched": [_vp, ctypes.c_char_p],
         "gpc_get_tuning": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+        "gpc_get_fallback": [_vp, ctypes.POINTER(_i32)],
         "gpc_trace_enable": [_vp, _i32],
         "gpc_trace_reset": [_vp],
         "gpc_trace_read": [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
@@ -165,6 +167,13 @@ class Handle:
         self._sync_stream()
         self._check(self.lib.gpc_factor(self.h, n, _ptr(A), lda, _ptr(info)), "gpc_factor")
         return info
+
+    def fell_back(self) -> bool:
+        """True if the last factor call was a mixed-precision one that lost
+        definiteness in its FP32 updates and was redone in FP64."""
+        f = _i32(0)
+        self._check(self.lib.gpc_get_fallback(self.h, ctypes.byref(f)), "gpc_get_fallback")
+        return bool(f.value)
 
     def adjoint(self, L: torch.Tensor, Lbar: torch.Tensor) -> torch.Tensor:
         """In place: tril(Lbar) <- Abar, strict upper <- 0.  Returns Lbar."""

@@ -41,6 +41,7 @@ def test_null_handle_and_bad_arguments_rejected():
     assert lib.gpc_destroy(None) == E
     assert lib.gpc_create(None, None) == E
     assert lib.gpc_set_options(None, None) == E
+    assert lib.gpc_get_fallback(None, None) == E
 
 
 def test_status_strings():
@@ -58,3 +59,11 @@ def test_create_without_device_reports_no_device():
     h = ctypes.c_void_p()
     assert lib.gpc_create(ctypes.byref(h), None) == gpchol.GPC_ERR_NO_DEVICE
     assert not h.value
+
+
+def test_options_struct_layout():
+    # the binding's struct mirrors gpc_options: four int32, a double, two int32
+    o = gpchol.gpc_options()
+    assert ctypes.sizeof(o) == 32
+    assert gpchol.gpc_options.refine_tol.offset == 16
+    assert gpchol.gpc_options.mixed_fallback.offset == 24

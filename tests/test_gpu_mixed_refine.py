@@ -110,3 +110,45 @@ def test_mixed_adjoint_given_factor_matches_fp64_closely(H):
     e = relf(host(Lbt), oracle.potrf_adjoint(L0, Lb))
     say(f"mixed adjoint given factor: {e:.2e}")
     assert e <= 1e-4
+
+
+def test_mixed_fallback_to_fp64():
+    """FP32 trailing updates lose definiteness on copied points with a tiny
+    nugget; the mixed factor then redoes the factorisation in FP64 (flag set),
+    giving exactly the FP64 path's L."""
+    from paper_1907_01063_amd import GPC_FP64, GPC_MIXED, Handle
+    case = W.matern_duplicates(1024, 64, 1e-10)
+    A = case["A"]
+    assert oracle.potrf(A)[1] == 0                      # SPD in FP64
+    say("mixed fallback n=1024")
+    Hm = Handle()
+    Hm.set_options(precision=GPC_MIXED, mixed_fallback=0)
+    At = dev(A)
+    info = int(host(Hm.factor(At)))
+    assert info != 0 and not Hm.fell_back()              # the FP32 form really breaks down
+    Hm.set_options(mixed_fallback=1)
+    At = dev(A)
+    info = int(host(Hm.factor(At)))
+    assert info == 0 and Hm.fell_back()
+    Hd = Handle()
+    Hd.set_options(precision=GPC_FP64)
+    Ad = dev(A)
+    assert int(host(Hd.factor(Ad))) == 0
+    assert torch.equal(At, Ad)
+    L = host(At)
+    rows = np.arange(0, 1024, 37)
+    assert np.linalg.norm(L[rows] @ L.T - A[rows]) / np.linalg.norm(A[rows]) <= 1e-13
+
+
+def test_mixed_no_fallback_when_definite(H):
+    case = W.c3(n=700)
+    mixed(H)
+    try:
+        At = dev(case["A"])
+        assert int(host(H.factor(At))) == 0
+        assert not H.fell_back()
+    finally:
+        fp64(H)
+    Lo, _ = oracle.potrf(case["A"])
+    e = relf(host(At), Lo)
+    assert 0.0 < e <= 1e-3                               # the FP32 result, not a silent FP64 redo

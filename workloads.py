@@ -122,6 +122,21 @@ def c3(seed: int = SEEDS["c3"], n: int = 16384, with_lbar: bool = True) -> dict:
     return {"name": f"matern32-2d-n{n}", "x": x, "A": A, "Lbar": Lbar, "y": y}
 
 
+def matern_duplicates(n: int = 1024, dup: int = 64, noise: float = 1e-10, seed: int = SEEDS["c3"]) -> dict:
+    """The n-point Matern-3/2 workload at the same point density, with points
+    n/2 .. n/2 + dup - 1 copies of points 0 .. dup - 1 and a nugget of `noise`:
+    each copied pair leaves a Schur-complement pivot of about `noise`, far
+    below FP32 rounding of the trailing updates (about 6e-8 here) but well
+    above FP64's, so the matrix is SPD in FP64 yet loses definiteness when its
+    updates are done in FP32."""
+    rng = np.random.default_rng(seed)
+    side = 50.0 * math.sqrt(n / 16384.0)
+    x = rng.uniform(0.0, side, size=(n, 2))
+    h = n // 2
+    x[h:h + dup] = x[:dup]
+    return {"name": f"matern32-dup{dup}-n{n}", "x": x, "A": matern32_cov(x, 1.0, 3.0, noise)}
+
+
 def c4(seed: int = SEEDS["c4"], count: int = 512, nmin: int = 32, nmax: int = 1024,
        with_lbar: bool = True) -> dict:
     """Batch of SE covariances of uneven order, packed row-major one after the
