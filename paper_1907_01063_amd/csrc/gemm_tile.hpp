@@ -2,6 +2,8 @@
 // batched kernel.  See gemm.hip for the scheme.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace gpc {
@@ -88,7 +90,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     auto sB = [&](int buf, int kk) -> RowB& { return sB0[buf * BK + kk]; };
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WN, wn = wave % WN;
 
     const int64_t m0 = tm * BM, n0 = tn * BN;
@@ -233,14 +235,40 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     }
 
     const int64_t nchunk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-    auto compute = [&](int cur) {
+    // LDS layouts.  Register path: both operands k-major, sA[k][m] and
+    // sB[k][n] (pitch BM + PAD).  Direct path (16-byte lane loads that go
+    // straight from memory into LDS): a KM or KN operand keeps the k-major
+    // layout, one 1 KB k-row per wave load; an MK or NK operand is stored
+    // row-major, its BK = 16 k values (128 B) per row, with the row's 16-byte
+    // pairs permuted by (row >> 1) & 7 so that the 16 rows one MFMA operand
+    // fetch touches fall into distinct banks.  Direct loads carry no sign
+    // flip, so the subtracting form negates A at the fragment read instead.
+    const int sw = (lc >> 1) & 7;     // pair permutation of the rows this lane reads
+    auto compute = [&](int cur, auto dir_tag) {
+        constexpr bool dir = decltype(dir_tag)::value;
+        const TI* rowA = &sA(cur, 0)[0];
+        const TI* rowB = &sB(cur, 0)[0];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
+            const int k = kk + lr;
             TI a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = sA(cur, kk + lr)[wm * WTM + i * 16 + lc];
+            for (int i = 0; i < FM; ++i) {
+                const int r = wm * WTM + i * 16 + lc;
+                if (dir && !AKM) {
+                    const TI x = rowA[r * BK + (((k >> 1) ^ sw) << 1) + (k & 1)];
+                    a[i] = kFold ? -x : x;
+                } else if (dir) {
+                    a[i] = kFold ? -sA(cur, k)[r] : sA(cur, k)[r];
+                } else {
+                    a[i] = sA(cur, k)[r];
+                }
+            }
 #pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = sB(cur, kk + lr)[wn * WTN + j * 16 + lc];
+            for (int j = 0; j < FN; ++j) {
+                const int c = wn * WTN + j * 16 + lc;
+                b[j] = (dir && BNK) ? rowB[c * BK + (((k >> 1) ^ sw) << 1) + (k & 1)] : sB(cur, k)[c];
+            }
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -248,7 +276,77 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                     acc[i][j] = Mfma<TI>::op(a[i], b[j], acc[i][j]);
         }
     };
-    if (nchunk > 0) {
+    typedef std::integral_constant<bool, true> DirectTag;
+    typedef std::integral_constant<bool, false> RegTag;
+
+    // direct path: FP64 128 x 128 tiles of 8 waves, 16-byte aligned rows,
+    // no per-element masks; KM/KN rows must be whole (16-byte pairs inside
+    // the operand), MK/NK k ranges even (pairs never straddle the k end)
+    constexpr bool kDirectShape = sizeof(TI) == 8 && BM == 128 && BN == 128 && NT == 512 && BK == 16;
+    bool direct = false;
+    if (kDirectShape && nchunk > 0 && g.a_lower == 0) {
+        const bool evenk = ((kend - kbeg) & 1) == 0;
+        const bool okA = ((uintptr_t)Ap & 15) == 0 && (g.lda & 1) == 0 &&
+                         (AKM ? (m0 + BM <= g.M && (g.head_k == 0 || (((uintptr_t)Hp & 15) == 0 && (g.ldah & 1) == 0)))
+                              : evenk);
+        const bool okB = ((uintptr_t)Bp & 15) == 0 && (g.ldb & 1) == 0 && (BNK ? evenk : n0 + BN <= g.N);
+        direct = okA && okB;
+    }
+    if (kDirectShape && direct) {
+        typedef __attribute__((address_space(3))) void lds_void;
+        // MK / NK: wave w fills rows 8w .. 8w+7 and 64+8w .. 64+8w+7; lane l
+        // takes row 8w + l/8 (+64) and stores its pair l%8, which holds the
+        // operand's k pair (l%8) ^ ((row >> 1) & 7)
+        const int rr = 8 * wave + (lane >> 3);
+        const int pp = (lane & 7) ^ ((rr >> 1) & 7);    // same for rr + 64
+        auto issue = [&](int64_t k0, int buf) {
+            const int krem = (int)(kend - k0);
+            TI* dA = &sA(buf, 0)[0];
+            TI* dB = &sB(buf, 0)[0];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (AKM) {
+                    const int kk = wave + 8 * h;
+                    const int64_t gk = k0 + kk;
+                    const TI* base = gk < g.head_k ? Hp + gk * g.ldah + m0 : Ap + (gk - g.head_k) * g.lda + m0;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(base), (lds_void*)&sA(buf, kk)[0], 16,
+                                                             kk < krem ? (uint32_t)lane * 16u : kOffOut, 0, 0, 0);
+                } else {
+                    const int r = rr + 64 * h;
+                    const uint32_t off = (m0 + r < g.M) & (2 * pp < krem)
+                                             ? (uint32_t)(r * g.lda + 2 * pp) * (uint32_t)sizeof(TI) : kOffOut;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Ap + m0 * g.lda + k0),
+                                                             (lds_void*)(dA + (8 * wave + 64 * h) * BK), 16, off, 0, 0, 0);
+                }
+                if (!BNK) {
+                    const int kk = wave + 8 * h;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Bp + (k0 + kk) * g.ldb + n0),
+                                                             (lds_void*)&sB(buf, kk)[0], 16,
+                                                             kk < krem ? (uint32_t)lane * 16u : kOffOut, 0, 0, 0);
+                } else {
+                    const int r = rr + 64 * h;
+                    const uint32_t off = (n0 + r < g.N) & (2 * pp < krem)
+                                             ? (uint32_t)(r * g.ldb + 2 * pp) * (uint32_t)sizeof(TI) : kOffOut;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Bp + n0 * g.ldb + k0),
+                                                             (lds_void*)(dB + (8 * wave + 64 * h) * BK), 16, off, 0, 0, 0);
+                }
+            }
+        };
+        issue(kbeg, 0);
+        if (kFold) load_c();
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's LDS loads landed
+        __syncthreads();
+        int64_t c = 0;
+        for (; c + 1 < nchunk; ++c) {
+            const int cur = (int)(c & 1);
+            issue(kbeg + (c + 1) * BK, cur ^ 1);
+            compute(cur, DirectTag());
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __syncthreads();
+        }
+        compute((int)(c & 1), DirectTag());
+        __syncthreads();
+    } else if (nchunk > 0) {
         load(kbeg);
         if (kFold) load_c();
         store(0);
@@ -260,11 +358,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
         for (; c + 1 < nchunk; ++c) {
             const int cur = (int)(c & 1);
             load(kbeg + (c + 1) * BK);
-            compute(cur);
+            compute(cur, RegTag());
             store(cur ^ 1);
             __syncthreads();
         }
-        compute((int)(c & 1));
+        compute((int)(c & 1), RegTag());
         __syncthreads();
     } else if (kFold) {
         load_c();
