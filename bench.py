@@ -251,7 +251,30 @@ def main():
         cfg["batched"] = {"workload": "se3d-batch512 n~U{32..1024} factor+adjoint", "matrices": len(bc["n"]),
                           "flops": Fb, "launch_ms": round(kms_b, 3), "ms_per_step_with_copies": round(msb, 3),
                           "value": round(Fb / (kms_b * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "form": "fp64"}
-        del base0, lbar0, bw, lw, bc, Hb
+        # the same batch in the mixed form (FP32 trailing / B-bar / R-bar products)
+        ref_l, ref_a = bw.clone(), lw.clone()
+        Hbm = Handle()
+        Hbm.set_options(precision=GPC_MIXED)
+
+        def stepbm():
+            bw.copy_(base0)
+            lw.copy_(lbar0)
+            Hbm.factor_adjoint_batched(bc["n"], bc["off"], bw, lw, binfo)
+
+        msbm = timed(stepbm, args.steps, args.warmup)
+        Hbm.trace_enable(True)
+        Hbm.trace_reset()
+        stepbm()
+        kms_bm = Hbm.trace_read()["batched"][1]
+        Hbm.trace_enable(False)
+        assert int(binfo.max().item()) == 0
+        el = (torch.linalg.norm(bw - ref_l) / torch.linalg.norm(ref_l)).item()
+        ea = (torch.linalg.norm(lw - ref_a) / torch.linalg.norm(ref_a)).item()
+        log(f"batched mixed: launch {kms_bm:.2f} ms, err vs fp64 batch: L {el:.2e} Abar {ea:.2e}")
+        cfg["batched"]["mixed"] = {"launch_ms": round(kms_bm, 3), "ms_per_step_with_copies": round(msbm, 3),
+                                   "value": round(Fb / (kms_bm * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                                   "err_vs_fp64_batch": {"L": el, "Abar": ea}}
+        del base0, lbar0, bw, lw, bc, Hb, Hbm, ref_l, ref_a
         torch.cuda.empty_cache()
 
         # ---- GP marginal log-likelihood gradient at n = 30000

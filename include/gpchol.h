@@ -173,7 +173,12 @@ gpc_status gpc_gp_hypergrad_se(gpc_handle* h, int64_t n, int32_t d, const double
  * later calls; if the handle's stream is itself being captured, the launch is
  * recorded into the caller's graph instead.  Results are bitwise independent
  * of queue order.  info_dev: nb device int32 (0 or first failing column + 1).
- * FP64 only. */
+ * The handle's precision applies: GPC_MIXED runs the trailing update and the
+ * B-bar / R-bar products in FP32 on MFMA (operands rounded from FP64 on load,
+ * FP32 accumulation subtracted from FP64 storage); diagonal blocks, panels and
+ * the diagonal reverse step stay FP64.  The batched mixed factor has no FP64
+ * fallback: a matrix whose FP32-updated Schur complement loses definiteness
+ * reports it in info. */
 gpc_status gpc_factor_batched(gpc_handle* h, int32_t nb, const int32_t* n_host, const int64_t* off_host,
                               double* base, int32_t* info_dev);
 gpc_status gpc_adjoint_batched(gpc_handle* h, int32_t nb, const int32_t* n_host, const int64_t* off_host,

@@ -927,6 +927,7 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
     for (int32_t i = 0; i < nb; ++i)
         if (n_host[i] < 0 || off_host[i] < 0) return GPC_ERR_ARG;
     if (nb == 0) return GPC_OK;
+    if (h->opt.precision == GPC_MIXED) mode |= 4;   // FP32 trailing and B-bar / R-bar products
     hipStream_t s = h->stream;
     std::vector<int32_t> blocks(h->tune_block, h->tune_block + kTuneBuckets);
     BatchPlan* p = h->plan;

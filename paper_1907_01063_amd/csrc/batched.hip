@@ -35,9 +35,12 @@ __device__ __forceinline__ GemmArgs ga(int64_t M, int64_t N, int64_t K, const do
 }
 
 // All tiles of an M x N product, one after the other, by this workgroup.
-template <bool AKM, bool BNK, int EPI, bool LOWER>
+// TI: MFMA type.  FP64 operands are converted on load when TI is float
+// (the mixed form's FP32 products, FP32 accumulation, subtracted from FP64 C).
+template <typename TI, bool AKM, bool BNK, int EPI, bool LOWER>
 __device__ void wg_gemm(const GemmArgs& g, double* lds)
 {
+    static_assert(TileLds<TI, 64, 64, 16>::elems * sizeof(TI) <= Lds64::elems * sizeof(double), "tile LDS");
     if (g.M <= 0 || g.N <= 0) return;
     const int64_t tM = (g.M + 63) / 64, tN = (g.N + 63) / 64;
     const int64_t count = LOWER ? tM * (tM + 1) / 2 : tM * tN;
@@ -45,7 +48,7 @@ __device__ void wg_gemm(const GemmArgs& g, double* lds)
         int64_t tm, tn;
         if (LOWER) lower_tile(t, tm, tn);
         else { tm = t / tN; tn = t % tN; }
-        gemm_tile<double, 64, 64, 16, 2, 2, AKM, BNK, EPI, LOWER>(g, tm, tn, 0, lds);
+        gemm_tile<TI, 64, 64, 16, 2, 2, AKM, BNK, EPI, LOWER, double>(g, tm, tn, 0, (TI*)lds);
     }
     __syncthreads();   // results visible to the whole workgroup
 }
@@ -62,6 +65,7 @@ struct Scratch {
     double *X, *P, *W, *S, *T, *M;   // 64 x 64 each
 };
 
+template <typename TU>   // type of the trailing update's products (double, or float in the mixed form)
 __device__ void factor_one(int n, int b, double* A, int32_t* info, const Scratch& w, double* lds,
                            double* colbuf, double* rowbuf, double* piv, double* rls)
 {
@@ -73,12 +77,13 @@ __device__ void factor_one(int n, int b, double* A, int32_t* info, const Scratch
         const int m = n - k - kb;
         if (m <= 0) continue;
         double* A21 = A + (int64_t)(k + kb) * lda + k;
-        wg_gemm<false, true, EPI_STORE, false>(ga(m, kb, kb, A21, lda, w.X, kBB, A21, lda), lds);
-        wg_gemm<false, true, EPI_SUB, true>(ga(m, m, kb, A21, lda, A21, lda, A21 + kb, lda), lds);
+        wg_gemm<double, false, true, EPI_STORE, false>(ga(m, kb, kb, A21, lda, w.X, kBB, A21, lda), lds);
+        wg_gemm<TU, false, true, EPI_SUB, true>(ga(m, m, kb, A21, lda, A21, lda, A21 + kb, lda), lds);
     }
     zero_upper_wg(n, A, lda);
 }
 
+template <typename TU>   // type of the B-bar and R-bar products (double, or float in the mixed form)
 __device__ void adjoint_one(int n, int b, const double* L, double* Lb, const Scratch& w, double* lds,
                             double* Ls, double* rowbuf)
 {
@@ -92,11 +97,11 @@ __device__ void adjoint_one(int n, int b, const double* L, double* Lb, const Scr
         diag_inverse<kBB / 16>(bq, D, ld, w.X, kBB, Ls, rowbuf);
         __syncthreads();
         if (nr > 0) {
-            wg_gemm<false, false, EPI_STORE, false>(ga(nr, bq, bq, Cbar, ld, w.X, kBB, Cbar, ld), lds);
+            wg_gemm<double, false, false, EPI_STORE, false>(ga(nr, bq, bq, Cbar, ld, w.X, kBB, Cbar, ld), lds);
             if (j > 0)
-                wg_gemm<false, false, EPI_SUB, false>(
+                wg_gemm<TU, false, false, EPI_SUB, false>(
                     ga(nr, j, bq, Cbar, ld, L + (int64_t)j * ld, ld, Lb + (int64_t)k * ld, ld), lds);
-            wg_gemm<true, false, EPI_STORE, false>(ga(bq, bq, nr, Cbar, ld, L + (int64_t)k * ld + j, ld, w.P, kBB),
+            wg_gemm<double, true, false, EPI_STORE, false>(ga(bq, bq, nr, Cbar, ld, L + (int64_t)k * ld + j, ld, w.P, kBB),
                                                    lds);
         }
         // W = tril(Dbar - Cbar^T C)
@@ -107,18 +112,18 @@ __device__ void adjoint_one(int n, int b, const double* L, double* Lb, const Scr
         __syncthreads();
         GemmArgs gp = ga(bq, bq, bq, D, ld, w.W, kBB, w.S, kBB);
         gp.a_lower = 1;
-        wg_gemm<true, false, EPI_SYMLOW, false>(gp, lds);
-        wg_gemm<false, false, EPI_STORE, false>(ga(bq, bq, bq, w.S, kBB, w.X, kBB, w.T, kBB), lds);
+        wg_gemm<double, true, false, EPI_SYMLOW, false>(gp, lds);
+        wg_gemm<double, false, false, EPI_STORE, false>(ga(bq, bq, bq, w.S, kBB, w.X, kBB, w.T, kBB), lds);
         GemmArgs gm = ga(bq, bq, bq, w.X, kBB, w.T, kBB, w.M, kBB);
         gm.C2 = Dbar;
         gm.ldc2 = ld;
-        wg_gemm<true, false, EPI_PHI, false>(gm, lds);
+        wg_gemm<double, true, false, EPI_PHI, false>(gm, lds);
         if (j > 0) {
             GemmArgs gr = ga(bq, j, bq + nr, Cbar, ld, L + (int64_t)j * ld, ld, Lb + (int64_t)j * ld, ld);
             gr.Ahead = w.M;
             gr.ldah = kBB;
             gr.head_k = bq;
-            wg_gemm<true, false, EPI_SUB, false>(gr, lds);
+            wg_gemm<TU, true, false, EPI_SUB, false>(gr, lds);
         }
     }
     zero_upper_wg(n, Lb, ld);
@@ -145,10 +150,14 @@ batched_kernel(int nb, const BatchTask* tasks, double* Abase, double* Lbbase, in
         if (mode & 1) {
             if (threadIdx.x == 0) info[T.idx] = 0;
             __syncthreads();
-            factor_one(T.n, T.block, Abase + T.off, info + T.idx, w, lds, colbuf, rowbuf, piv, rls);
+            if (mode & 4) factor_one<float>(T.n, T.block, Abase + T.off, info + T.idx, w, lds, colbuf, rowbuf, piv, rls);
+            else factor_one<double>(T.n, T.block, Abase + T.off, info + T.idx, w, lds, colbuf, rowbuf, piv, rls);
             __syncthreads();
         }
-        if (mode & 2) adjoint_one(T.n, T.block, Abase + T.off, Lbbase + T.off, w, lds, Ls, rowbuf);
+        if (mode & 2) {
+            if (mode & 4) adjoint_one<float>(T.n, T.block, Abase + T.off, Lbbase + T.off, w, lds, Ls, rowbuf);
+            else adjoint_one<double>(T.n, T.block, Abase + T.off, Lbbase + T.off, w, lds, Ls, rowbuf);
+        }
     }
 }
 

@@ -69,7 +69,9 @@ struct TileLds {
 // One BM x BN output tile (tile row tm, tile column tn, split slice z) computed
 // by the whole workgroup (WM x WN waves).  lds: TileLds<...>::elems elements.
 // Ends with all LDS reads done, so calls may follow each other directly.
-template <typename TI, int BM, int BN, int BK, int WM, int WN, bool AKM, bool BNK, int EPI, bool LOWER>
+// TG: element type of A and B in memory (default TI); loads convert to TI.
+template <typename TI, int BM, int BN, int BK, int WM, int WN, bool AKM, bool BNK, int EPI, bool LOWER,
+          typename TG = TI>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t tn, int64_t z, TI* lds)
 {
     constexpr int NT = WM * WN * 64;
@@ -98,9 +100,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     const int64_t kend = min(g.K, kbeg + g.kchunk);
 
     // no __restrict__: the in-place panel products write the rows they read
-    const TI* Ap = (const TI*)g.A;
-    const TI* Hp = (const TI*)g.Ahead;
-    const TI* Bp = (const TI*)g.B;
+    const TG* Ap = (const TG*)g.A;
+    const TG* Hp = (const TG*)g.Ahead;
+    const TG* Bp = (const TG*)g.B;
 
     // Thread-constant parts of the load coordinates.  A element p of this
     // thread is (row mA + p*ASTEP, k kA) for MK or (row mA, k kA + p*ASTEP)
@@ -117,14 +119,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
         const int r = AKM ? kA + p * ASTEP : mA + p * ASTEP;   // stored row within the chunk/tile
         const int c = AKM ? mA : kA;
         const bool v = AKM ? (m0 + mA < g.M) : (m0 + mA + p * ASTEP < g.M);
-        offA[p] = v ? (uint32_t)(r * g.lda + c) * (uint32_t)sizeof(TI) : kOffOut;
+        offA[p] = v ? (uint32_t)(r * g.lda + c) * (uint32_t)sizeof(TG) : kOffOut;
     }
 #pragma unroll
     for (int p = 0; p < LB; ++p) {
         const int r = BNK ? nB + p * BSTEP : kB + p * BSTEP;
         const int c = BNK ? kB : nB;
         const bool v = BNK ? (n0 + nB + p * BSTEP < g.N) : (n0 + nB < g.N);
-        offB[p] = v ? (uint32_t)(r * g.ldb + c) * (uint32_t)sizeof(TI) : kOffOut;
+        offB[p] = v ? (uint32_t)(r * g.ldb + c) * (uint32_t)sizeof(TG) : kOffOut;
     }
 
     TI ra[LA], rb[LB];
@@ -148,20 +150,20 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
             for (int p = 0; p < LA; ++p) {
                 const int kk = kA + p * ASTEP;
                 in[p] = (offA[p] != kOffOut) & (kk < krem) & !(alow & (dA - p * ASTEP > dmk));
-                oh[p] = in[p] & (kk < hrem) ? (uint32_t)(kk * g.ldah + mA) * (uint32_t)sizeof(TI) : kOffOut;
+                oh[p] = in[p] & (kk < hrem) ? (uint32_t)(kk * g.ldah + mA) * (uint32_t)sizeof(TG) : kOffOut;
             }
             if (hrem >= BK) {            // whole chunk in the head
 #pragma unroll
-                for (int p = 0; p < LA; ++p) ra[p] = buffer_ld<TI>(rh, oh[p]);
+                for (int p = 0; p < LA; ++p) ra[p] = (TI)buffer_ld<TG>(rh, oh[p]);
             } else {                     // chunk straddles the end of the head
                 const auto rm = operand_rsrc(Ap + m0);
                 TI h[LA];
 #pragma unroll
                 for (int p = 0; p < LA; ++p) {
                     const int kk = kA + p * ASTEP;
-                    const uint32_t om = in[p] & (kk >= hrem) ? (uint32_t)((kk - hrem) * g.lda + mA) * (uint32_t)sizeof(TI) : kOffOut;
-                    h[p] = buffer_ld<TI>(rh, oh[p]);
-                    ra[p] = buffer_ld<TI>(rm, om);
+                    const uint32_t om = in[p] & (kk >= hrem) ? (uint32_t)((kk - hrem) * g.lda + mA) * (uint32_t)sizeof(TG) : kOffOut;
+                    h[p] = (TI)buffer_ld<TG>(rh, oh[p]);
+                    ra[p] = (TI)buffer_ld<TG>(rm, om);
                 }
 #pragma unroll
                 for (int p = 0; p < LA; ++p) ra[p] += h[p];   // one of the two is zero
@@ -177,7 +179,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
             }
             const auto rs = operand_rsrc(AKM ? Ap + (k0 - g.head_k) * g.lda + m0 : Ap + m0 * g.lda + k0);
 #pragma unroll
-            for (int p = 0; p < LA; ++p) ra[p] = buffer_ld<TI>(rs, o[p]);
+            for (int p = 0; p < LA; ++p) ra[p] = (TI)buffer_ld<TG>(rs, o[p]);
         }
         // B
         uint32_t o[LB];
@@ -185,15 +187,20 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
         for (int p = 0; p < LB; ++p) o[p] = (BNK ? kB < krem : kB < krem - p * BSTEP) ? offB[p] : kOffOut;
         const auto rs = operand_rsrc(BNK ? Bp + n0 * g.ldb + k0 : Bp + k0 * g.ldb + n0);
 #pragma unroll
-        for (int p = 0; p < LB; ++p) rb[p] = buffer_ld<TI>(rs, o[p]);
+        for (int p = 0; p < LB; ++p) rb[p] = (TI)buffer_ld<TG>(rs, o[p]);
     };
     // FP64 subtract: the accumulators start at C and the MFMAs are fed -A,
     // so they form C - A B directly and the epilogue only writes.  The C
     // loads are issued right after the first operand chunk's, so their
     // latency overlaps it instead of following the last MFMA.
     constexpr bool kFold = EPI == EPI_SUB && sizeof(TI) == 8;
+    // FP32 subtract from FP64 C, small tiles: C is read into FP64 registers at
+    // the same point (there is room for them in a 64 x 64 tile) and the
+    // epilogue writes C - A B without a read of its own
+    constexpr bool kPre = EPI == EPI_SUB && sizeof(TI) == 4 && FM * FN <= 4;
     typedef typename Mfma<TI>::acc_t acc_t;
     acc_t acc[FM][FN];
+    double cpre[kPre ? FM : 1][kPre ? FN : 1][4];
     const int lr = lane >> 4, lc = lane & 15;
     auto load_c = [&]() {
         const auto rc = operand_rsrc(g.C + m0 * g.ldc + n0);
@@ -208,8 +215,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                     const int row = wm * WTM + i * 16 + Mfma<TI>::row(lr, r);
                     const int col = wn * WTN + j * 16 + lc;
                     const bool in = (m0 + row < g.M) & (n0 + col < g.N) & !(lowc & (n0 + col > m0 + row));
-                    acc[i][j][r] = (typename Mfma<TI>::elem_t)buffer_ld<double>(
-                        rc, in ? (uint32_t)row * ldc8 + (uint32_t)col * 8u : kOffOut);
+                    const double cv = buffer_ld<double>(rc, in ? (uint32_t)row * ldc8 + (uint32_t)col * 8u : kOffOut);
+                    if (kPre) cpre[kPre ? i : 0][kPre ? j : 0][r] = cv;
+                    else acc[i][j][r] = (typename Mfma<TI>::elem_t)cv;
                 }
     };
     auto store = [&](int buf) {
@@ -282,7 +290,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     // direct path: FP64 128 x 128 tiles of 8 waves, 16-byte aligned rows,
     // no per-element masks; KM/KN rows must be whole (16-byte pairs inside
     // the operand), MK/NK k ranges even (pairs never straddle the k end)
-    constexpr bool kDirectShape = sizeof(TI) == 8 && BM == 128 && BN == 128 && NT == 512 && BK == 16;
+    constexpr bool kDirectShape = sizeof(TI) == 8 && sizeof(TG) == 8 && BM == 128 && BN == 128 && NT == 512 && BK == 16;
     bool direct = false;
     if (kDirectShape && nchunk > 0 && g.a_lower == 0) {
         const bool evenk = ((kend - kbeg) & 1) == 0;
@@ -308,13 +316,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                 if (AKM) {
                     const int kk = wave + 8 * h;
                     const int64_t gk = k0 + kk;
-                    const TI* base = gk < g.head_k ? Hp + gk * g.ldah + m0 : Ap + (gk - g.head_k) * g.lda + m0;
+                    const TG* base = gk < g.head_k ? Hp + gk * g.ldah + m0 : Ap + (gk - g.head_k) * g.lda + m0;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(base), (lds_void*)&sA(buf, kk)[0], 16,
                                                              kk < krem ? (uint32_t)lane * 16u : kOffOut, 0, 0, 0);
                 } else {
                     const int r = rr + 64 * h;
                     const uint32_t off = (m0 + r < g.M) & (2 * pp < krem)
-                                             ? (uint32_t)(r * g.lda + 2 * pp) * (uint32_t)sizeof(TI) : kOffOut;
+                                             ? (uint32_t)(r * g.lda + 2 * pp) * (uint32_t)sizeof(TG) : kOffOut;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Ap + m0 * g.lda + k0),
                                                              (lds_void*)(dA + (8 * wave + 64 * h) * BK), 16, off, 0, 0, 0);
                 }
@@ -326,14 +334,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                 } else {
                     const int r = rr + 64 * h;
                     const uint32_t off = (n0 + r < g.N) & (2 * pp < krem)
-                                             ? (uint32_t)(r * g.ldb + 2 * pp) * (uint32_t)sizeof(TI) : kOffOut;
+                                             ? (uint32_t)(r * g.ldb + 2 * pp) * (uint32_t)sizeof(TG) : kOffOut;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Bp + n0 * g.ldb + k0),
                                                              (lds_void*)(dB + (8 * wave + 64 * h) * BK), 16, off, 0, 0, 0);
                 }
             }
         };
         issue(kbeg, 0);
-        if (kFold) load_c();
+        if (kFold || kPre) load_c();
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's LDS loads landed
         __syncthreads();
         int64_t c = 0;
@@ -348,7 +356,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
         __syncthreads();
     } else if (nchunk > 0) {
         load(kbeg);
-        if (kFold) load_c();
+        if (kFold || kPre) load_c();
         store(0);
         __syncthreads();
         // the last chunk is peeled off, so every iteration's loads are
@@ -364,7 +372,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
         }
         compute((int)(c & 1), RegTag());
         __syncthreads();
-    } else if (kFold) {
+    } else if (kFold || kPre) {
         load_c();
     }
 
@@ -382,6 +390,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                 const double v = (double)acc[i][j][r];
                 if (EPI == EPI_SUB) {
                     if (kFold) g.C[row * g.ldc + col] = v;
+                    else if (kPre) g.C[row * g.ldc + col] = cpre[kPre ? i : 0][kPre ? j : 0][r] - v;
                     else g.C[row * g.ldc + col] -= v;
                 } else if (EPI == EPI_STORE) {
                     g.C[row * g.ldc + col] = v;

@@ -140,3 +140,35 @@ def test_full_size_batch_sampled(H):
         Lo, _ = oracle.potrf(A)
         assert relf(a[o:o + k * k].reshape(k, k), Lo) <= TOL
         assert relf(lb[o:o + k * k].reshape(k, k), oracle.potrf_adjoint(Lo, Lb)) <= TOL
+
+
+def test_batched_mixed_form():
+    """GPC_MIXED batch: FP32 trailing / B-bar / R-bar products.  No oracle of
+    its own (parity unpinned): error against the FP64 oracle within the mixed
+    budget of the single-matrix tests (L 1e-3, Abar 1e-2), nonzero (the FP32
+    products really ran) for matrices beyond one inner block, queue-order
+    independent, and bitwise stable across graph replays."""
+    from paper_1907_01063_amd import GPC_MIXED, Handle
+    Hm = Handle()
+    Hm.set_options(precision=GPC_MIXED)
+    As, Lbs = make_batch(6, SIZES)
+    say("batched mixed")
+    Ls, Abs, info = run(Hm, As, Lbs, SIZES)
+    assert np.all(info == 0)
+    for k, A, Lb, Lg, Ag in zip(SIZES, As, Lbs, Ls, Abs):
+        if k == 0:
+            continue
+        Lo, _ = oracle.potrf(A)
+        Ao = oracle.potrf_adjoint(Lo, Lb)
+        eL, eA = relf(Lg, Lo), relf(Ag, Ao)
+        assert np.all(np.triu(Lg, 1) == 0) and np.all(np.triu(Ag, 1) == 0)
+        assert eL <= 1e-3 and eA <= 1e-2, (k, eL, eA)
+        if k > 64:
+            assert eL > 1e-12, k
+    Ls2, Ab2, _ = run(Hm, As, Lbs, SIZES)
+    assert all(np.array_equal(x, y) for x, y in zip(Ls, Ls2))
+    assert all(np.array_equal(x, y) for x, y in zip(Abs, Ab2))
+    perm = np.random.default_rng(2).permutation(len(SIZES))
+    Ls3, Ab3, _ = run(Hm, [As[i] for i in perm], [Lbs[i] for i in perm], [SIZES[i] for i in perm])
+    for pos, i in enumerate(perm):
+        assert np.array_equal(Ls3[pos], Ls[i]) and np.array_equal(Ab3[pos], Abs[i])
