@@ -209,6 +209,17 @@ def main():
                "refined_solve": round(timed(lambda: Hm.solve_refined(A0, Lm, y0, x=xr, check=False), 2, 0), 3),
                "adjoint": round(timed(lambda: (Lbm.copy_(Lb0), Hm.adjoint(Lm, Lbm)), 2, 0) - cpm, 3)}
         log(f"mixed phases (ms): {phm}")
+        trm = None
+        if not args.no_trace:
+            # per-class kernel time of the mixed step, serial schedule (as for FP64)
+            Hm.set_options(lookahead=0)
+            Hm.trace_enable(True)
+            Hm.trace_reset()
+            stepmix()
+            trm = {k: round(v[1], 3) for k, v in Hm.trace_read().items() if v[0]}
+            Hm.trace_enable(False)
+            Hm.set_options(lookahead=args.lookahead)
+            log(f"mixed trace classes (ms): {trm}")
         it, etam = int(out["it"].item()), float(out["eta"].item())
         eL = (torch.linalg.norm(Lm - L) / torch.linalg.norm(L)).item()
         eA = (torch.linalg.norm(Lbm - Lb) / torch.linalg.norm(Lb)).item()
@@ -218,7 +229,7 @@ def main():
             f"err vs fp64: L {eL:.2e} Abar {eA:.2e} alpha {ea:.2e}")
         cfg["mixed"] = {"value": round(vm, 2), "unit": "GFLOP/s", "ms_per_step": round(msm, 3),
                         "speedup_vs_fp64": round(ms / msm, 3), "refine_iters": it, "refined_eta_inf": etam,
-                        "phases_ms": phm,
+                        "phases_ms": phm, "classes_ms": trm,
                         "err_vs_fp64_path": {"L": eL, "Abar": eA, "alpha": ea},
                         "step": "factor (FP32 trailing updates) + FP64-refined solve + log-det + adjoint"}
         del Lm, Lbm, Hm

@@ -67,12 +67,12 @@ struct Scratch {
 
 template <typename TU>   // type of the trailing update's products (double, or float in the mixed form)
 __device__ void factor_one(int n, int b, double* A, int32_t* info, const Scratch& w, double* lds,
-                           double* colbuf, double* rowbuf, double* piv, double* rls)
+                           double* colbuf, double* rowbuf, double* rls)
 {
     const int64_t lda = n;
     for (int k = 0; k < n; k += b) {
         const int kb = min(b, n - k);
-        diag_factor_inverse<kBB / 16>(kb, A + k * lda + k, lda, w.X, kBB, info, k, colbuf, rowbuf, piv, rls);
+        diag_factor_inverse_g4<kBB / 16>(kb, A + k * lda + k, lda, w.X, kBB, info, k, colbuf, rowbuf, rls);
         __syncthreads();
         const int m = n - k - kb;
         if (m <= 0) continue;
@@ -135,7 +135,7 @@ batched_kernel(int nb, const BatchTask* tasks, double* Abase, double* Lbbase, in
 {
     __shared__ double lds[Lds64::elems];
     __shared__ double Ls[kBB * (kBB + 1)];
-    __shared__ double colbuf[2 * kBB], rowbuf[2 * kBB], piv[4], rls[kBB];
+    __shared__ double colbuf[2 * 4 * kBB], rowbuf[2 * 4 * kBB], rls[kBB];
     __shared__ int s_task;
     double* mine = ws + (int64_t)blockIdx.x * 6 * kBB * kBB;
     const Scratch w{mine, mine + kBB * kBB, mine + 2 * kBB * kBB, mine + 3 * kBB * kBB, mine + 4 * kBB * kBB,
@@ -150,8 +150,8 @@ batched_kernel(int nb, const BatchTask* tasks, double* Abase, double* Lbbase, in
         if (mode & 1) {
             if (threadIdx.x == 0) info[T.idx] = 0;
             __syncthreads();
-            if (mode & 4) factor_one<float>(T.n, T.block, Abase + T.off, info + T.idx, w, lds, colbuf, rowbuf, piv, rls);
-            else factor_one<double>(T.n, T.block, Abase + T.off, info + T.idx, w, lds, colbuf, rowbuf, piv, rls);
+            if (mode & 4) factor_one<float>(T.n, T.block, Abase + T.off, info + T.idx, w, lds, colbuf, rowbuf, rls);
+            else factor_one<double>(T.n, T.block, Abase + T.off, info + T.idx, w, lds, colbuf, rowbuf, rls);
             __syncthreads();
         }
         if (mode & 2) {
