@@ -792,12 +792,14 @@ gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const
     const int b = kDiagMax;   // solves sweep 128-blocks
     const int64_t nblk = (n + b - 1) / b;
     const size_t n_dinv = (size_t)nblk * b * b;
-    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + (size_t)trsm_workspace(n)));
+    gpc_status st = ensure_ws(h, sizeof(double) * (2 * n_dinv + (size_t)trsm_workspace(n)));
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
-    double* Y = Dinv + n_dinv;
+    double* Cpl = Dinv + n_dinv;
+    double* Y = Cpl + n_dinv;
     GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
-    GPC_HIP(h, trsm_blocked(s, trans, n, nrhs, L, ldl, Dinv, b, B, ldb, Y));
+    GPC_HIP(h, trsm_couplings(s, trans, n, L, ldl, Dinv, b, Cpl));
+    GPC_HIP(h, trsm_blocked(s, trans, n, nrhs, L, ldl, Dinv, Cpl, b, B, ldb, Y));
     return GPC_OK;
 }
 
@@ -828,15 +830,19 @@ gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, 
         const int b = kDiagMax;   // solves sweep 128-blocks
         const int64_t nblk = (n + b - 1) / b;
         const size_t n_dinv = (size_t)nblk * b * b;
-        gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + (size_t)trsm_workspace(n)));
+        gpc_status st = ensure_ws(h, sizeof(double) * (3 * n_dinv + (size_t)trsm_workspace(n)));
         if (st != GPC_OK) return st;
         double* Dinv = (double*)h->ws;
-        double* Y = Dinv + n_dinv;
+        double* Cf = Dinv + n_dinv;
+        double* Cb = Cf + n_dinv;
+        double* Y = Cb + n_dinv;
         GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+        GPC_HIP(h, trsm_couplings(s, 0, n, L, ldl, Dinv, b, Cf));
+        GPC_HIP(h, trsm_couplings(s, 1, n, L, ldl, Dinv, b, Cb));
         GPC_HIP(h, vec_copy(s, n, y, z));
-        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, b, z, 1, Y));
+        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, z, 1, Y));
         GPC_HIP(h, vec_copy(s, n, z, alpha));
-        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, b, alpha, 1, Y));
+        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, alpha, 1, Y));
     }
     GPC_HIP(h, logdet(s, n, L, ldl, logdet_out));
     GPC_HIP(h, gp_value(s, n, z, logdet_out, f_out));
@@ -884,15 +890,19 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
     const int64_t nblk = (n + b - 1) / b;
     const size_t n_dinv = (size_t)nblk * b * b;
     const size_t n_part = (size_t)symv_parts(n);
-    gpc_status st = ensure_ws(h, sizeof(double) * (n_dinv + (size_t)trsm_workspace(n) + n_part + 3 * (size_t)n));
+    gpc_status st = ensure_ws(h, sizeof(double) * (3 * n_dinv + (size_t)trsm_workspace(n) + n_part + 3 * (size_t)n));
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
-    double* Y = Dinv + n_dinv;
+    double* Cf = Dinv + n_dinv;
+    double* Cb = Cf + n_dinv;
+    double* Y = Cb + n_dinv;
     double* part = Y + trsm_workspace(n);
     double* rowabs = part + n_part;
     double* r = rowabs + n;
     double* d = r + n;
     GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+    GPC_HIP(h, trsm_couplings(s, 0, n, L, ldl, Dinv, b, Cf));
+    GPC_HIP(h, trsm_couplings(s, 1, n, L, ldl, Dinv, b, Cb));
     GPC_HIP(h, symv_lower(s, n, K, ldk, nullptr, 1, nullptr, 1.0, rowabs, part));
     GPC_HIP(h, vec_zero(s, n, x));
     GPC_HIP(h, vec_copy(s, n, y, r));
@@ -902,8 +912,8 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
     while (it < maxit) {
         ++it;
         GPC_HIP(h, vec_copy(s, n, r, d));
-        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, b, d, 1, Y));
-        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, b, d, 1, Y));
+        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, d, 1, Y));
+        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, d, 1, Y));
         GPC_HIP(h, vec_axpy(s, n, d, x));
         GPC_HIP(h, symv_lower(s, n, K, ldk, x, 0, y, -1.0, r, part));
         GPC_HIP(h, refine_eta(s, n, r, x, y, rowabs, eta));

@@ -80,12 +80,18 @@ hipError_t reduce_tril(hipStream_t s, int b, const double* D, int64_t ldd, const
                        int S, int64_t pstride, double* W);
 
 // ---- solves and log-determinant --------------------------------------------
-// B <- L^-1 B (trans 0) or L^-T B (trans 1) by block steps with the diagonal
-// block inverses Dinv (as from trtri_diag_batched, block b).  Y: workspace of
+// Coupling blocks of the solves (b x b each at C + q*b*b, from the diagonal
+// block inverses Dinv of trtri_diag_batched): trans 0: Cf_q = Dinv_q L_{q,q-1}
+// (q >= 1); trans 1: Cb_q = L_{q+1,q} Dinv_q (q <= nblk-2).
+hipError_t trsm_couplings(hipStream_t s, int trans, int64_t n, const double* L, int64_t ldl,
+                          const double* Dinv, int b, double* C);
+// B <- L^-1 B (trans 0) or L^-T B (trans 1) by block steps with Dinv and the
+// couplings of the same direction (block b = kDiagMax).  Y: workspace of
 // trsm_workspace(n) doubles.
 int64_t trsm_workspace(int64_t n);
 hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L,
-                        int64_t ldl, const double* Dinv, int b, double* B, int64_t ldb, double* Y);
+                        int64_t ldl, const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb,
+                        double* Y);
 // *out = 2 * sum_i log L_ii (fixed summation order).
 hipError_t logdet(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* out);
 

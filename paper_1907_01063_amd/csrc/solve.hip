@@ -1,15 +1,19 @@
 // Triangular solves with the factor and the log-determinant (the pieces a GP
 // log-density needs: z = L^-1 y, alpha = L^-T z, log|K| = 2 sum log L_ii).
 //
-// The solves sweep the diagonal blocks of L (section 3.2 solves A x = b
-// through the inverse of the triangle; here only the b x b diagonal blocks are
+// The solves sweep the b x b diagonal blocks of L (section 3.2 solves A x = b
+// through the inverse of the triangle; here only the diagonal blocks are
 // inverted, and the off-diagonal blocks are applied as matrix-vector
-// updates).  One launch per block step q, with lookahead: the step's small
-// product z_q = D_q^-1 y_q (or D_q^-T y_q) was computed by the previous launch,
-// so workgroup 0 of launch q applies z_q to the rows of the next block only and
-// then forms z_{q+1} (double-buffered), while the other workgroups apply z_q to
-// their share of the remaining rows.  The running right-hand side lives in a
-// separate workspace; every reduction has a fixed order.
+// updates).  One launch per block step q, with lookahead: with the coupling
+// blocks Cf_{q+1} = Dinv_{q+1} L_{q+1,q} formed beforehand, the next block's
+// solution is z_{q+1} = Dinv_{q+1} y_{q+1} - Cf_{q+1} z_q, where y_{q+1}
+// already holds the updates of all earlier blocks.  So in launch q a few
+// workgroups each form 16 rows of z_{q+1} directly from z_q, with no wait on
+// anything else in the launch, while the other workgroups apply z_q to the
+// rows below block q+1.  The transposed sweep is the mirror image with
+// Cb_q = L_{q+1,q} Dinv_q (x_{q-1} = Dinv_{q-1}^T y_{q-1} - Cb_{q-1}^T x_q).
+// The running right-hand side lives in a separate workspace; every
+// reduction has a fixed order.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -69,57 +73,6 @@ __device__ void fwd_rows(int64_t r0, int64_t r1, int64_t j, int bq, int nr, cons
     }
 }
 
-// z_out = D^-1 y for the block rows [j, j+bq) of Y; writes z_out and B.
-__device__ void fwd_diag(int64_t j, int bq, int nr, const double* Dq, int b, const double* Y, int64_t ldy,
-                         double (*ys)[kRhsGroup], double* zout, double* B, int64_t ldb)
-{
-    for (int e = threadIdx.x; e < bq * nr; e += 256) ys[e / nr][e % nr] = Y[(j + e / nr) * ldy + e % nr];
-    __syncthreads();
-    const int q = threadIdx.x & 3;
-    for (int i0 = 0; i0 < bq; i0 += 64) {
-        const int i = i0 + (threadIdx.x >> 2);
-        double acc[kRhsGroup];
-        if (i < bq) quarter_dot(Dq + (int64_t)i * b, i + 1, q, nr, ys, acc);   // D^-1 is lower
-        else for (int c = 0; c < nr; ++c) acc[c] = 0.0;
-        for (int c = 0; c < nr; ++c) {
-            const double t = quad_sum(acc[c]);
-            if (q == 0 && i < bq) {
-                zout[i * kRhsGroup + c] = t;
-                B[(j + i) * ldb + c] = t;
-            }
-        }
-    }
-}
-
-// Prologue of the forward sweep: z_0 from the first block.
-__global__ void __launch_bounds__(256)
-trsv_fwd_first(int nr, int bq, const double* D0, int b, const double* Y, int64_t ldy, double* zbuf, double* B,
-               int64_t ldb)
-{
-    __shared__ double ys[kDiagMax][kRhsGroup];
-    fwd_diag(0, bq, nr, D0, b, Y, ldy, ys, zbuf, B, ldb);
-}
-
-// Step q of the forward sweep (block rows [j, j+bq), next block [j+bq, j+bq+bq1)).
-__global__ void __launch_bounds__(256)
-trsv_fwd_step(int64_t n, int nr, int64_t j, int bq, int bq1, const double* L, int64_t ldl, const double* Dnext,
-              int b, double* Y, int64_t ldy, const double* zcur, double* znext, double* B, int64_t ldb)
-{
-    __shared__ double z[kDiagMax][kRhsGroup];
-    __shared__ double ys[kDiagMax][kRhsGroup];
-    for (int e = threadIdx.x; e < bq * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
-    __syncthreads();
-    const int64_t jn = j + bq;
-    if (blockIdx.x == 0) {
-        fwd_rows(jn, jn + bq1, j, bq, nr, L, ldl, z, Y, ldy);
-        __syncthreads();
-        fwd_diag(jn, bq1, nr, Dnext, b, Y, ldy, ys, znext, B, ldb);
-    } else {
-        const int64_t r0 = jn + bq1 + (int64_t)(blockIdx.x - 1) * kRows;
-        fwd_rows(r0, min(n, r0 + kRows), j, bq, nr, L, ldl, z, Y, ldy);
-    }
-}
-
 // acc[c] = sum_t L[j+t][r] z[t][c] over t in [t0, t1) for one column r
 // (t1 - t0 <= 32); the loads are independent and issued together.
 __device__ __forceinline__ void bwd_col(int64_t r, int64_t j, int t0, int t1, int nr, const double* L, int64_t ldl,
@@ -156,73 +109,154 @@ __device__ void bwd_cols(int64_t r0, int64_t r1, int64_t j, int bq, int nr, cons
     __syncthreads();
 }
 
-// z_out = D^-T y for the block [j, j+bq) of Y; writes z_out and B.
-__device__ void bwd_diag(int64_t j, int bq, int nr, const double* Dq, int b, const double* Y, int64_t ldy,
-                         double (*ys)[kRhsGroup], double (*red)[64][kRhsGroup], double* zout, double* B,
+constexpr int kLook = 8;        // lookahead workgroups (16 rows of the next block each)
+
+// Forward lookahead: rows [i0, i0+16) of z_next = Dinv y_next - Cf z_cur for
+// the block [jn, jn + bn) (bn <= 128 rows; z_cur has bc entries, 0 if none).
+// 16 threads per row, thread k-slot s covers columns s, s+16, ...; the 16
+// partial sums of a row are combined in a fixed order.
+__device__ void fwd_look(int i0, int bn, int bc, int nr, const double* Dn, const double* Cf, int b,
+                         const double* Y, int64_t jn, int64_t ldy, const double* zcur, double* znext, double* B,
                          int64_t ldb)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int e = threadIdx.x; e < bq * nr; e += 256) ys[e / nr][e % nr] = Y[(j + e / nr) * ldy + e % nr];
+    __shared__ double ys[kDiagMax][kRhsGroup];
+    __shared__ double zs[kDiagMax][kRhsGroup];
+    for (int e = threadIdx.x; e < kDiagMax * kRhsGroup; e += 256) {
+        const int r = e / kRhsGroup, c = e % kRhsGroup;
+        ys[r][c] = (r < bn && c < nr) ? Y[(jn + r) * ldy + c] : 0.0;
+        zs[r][c] = (r < bc && c < nr) ? zcur[e] : 0.0;
+    }
     __syncthreads();
-    // z[i] = sum_{t >= i} D[t][i] y[t]: columns i over lanes (two halves), t over waves
-    for (int h = 0; h < 2; ++h) {
-        const int i = h * 64 + lane;
-        const int q4 = (bq + 3) / 4;
-        const int t0 = min(bq, wave * q4), t1 = min(bq, t0 + q4);
-        double acc[kRhsGroup];
-        for (int c = 0; c < nr; ++c) acc[c] = 0.0;
-        if (i < bq) {
-            double v[32];
+    const int sl = threadIdx.x & 15;
+    const int i = i0 + (threadIdx.x >> 4);
+    double acc[kRhsGroup];
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                const int t = t0 + k;
-                v[k] = (t < t1 && t >= i) ? Dq[(int64_t)t * b + i] : 0.0;   // D^-1 is lower
-            }
-            for (int c = 0; c < nr; ++c) {
-                double sacc = 0.0;
+    for (int c = 0; c < kRhsGroup; ++c) acc[c] = 0.0;
+    if (i < bn) {
+        double dv[kDiagMax / 16], cv[kDiagMax / 16];
 #pragma unroll
-                for (int k = 0; k < 32; ++k) sacc += v[k] * (t0 + k < t1 ? ys[t0 + k][c] : 0.0);
-                acc[c] = sacc;
-            }
+        for (int m = 0; m < kDiagMax / 16; ++m) {
+            const int k = sl + 16 * m;
+            dv[m] = k <= i ? Dn[(int64_t)i * b + k] : 0.0;            // Dinv is lower
+            cv[m] = (Cf && k < bc) ? Cf[(int64_t)i * b + k] : 0.0;
         }
-        for (int c = 0; c < nr; ++c) red[wave][lane][c] = acc[c];
-        __syncthreads();
-        if (wave == 0 && i < bq)
-            for (int c = 0; c < nr; ++c) {
-                const double p = ((red[0][lane][c] + red[1][lane][c]) + red[2][lane][c]) + red[3][lane][c];
-                zout[i * kRhsGroup + c] = p;
-                B[(j + i) * ldb + c] = p;
-            }
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kRhsGroup; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int m = 0; m < kDiagMax / 16; ++m) t += dv[m] * ys[sl + 16 * m][c] - cv[m] * zs[sl + 16 * m][c];
+            acc[c] = t;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kRhsGroup; ++c) {
+        double v = acc[c];
+#pragma unroll
+        for (int w = 1; w < 16; w <<= 1) {
+            const double o = __shfl_xor(v, w, 64);
+            v = (sl & w) ? o + v : v + o;
+        }
+        acc[c] = v;
+    }
+    if (sl == 0 && i < bn)
+        for (int c = 0; c < nr; ++c) {
+            znext[i * kRhsGroup + c] = acc[c];
+            B[(jn + i) * ldb + c] = acc[c];
+        }
+}
+
+// Backward lookahead: rows [i0, i0+16) of x_prev = Dinv^T y_prev - Cb^T x_cur
+// for the full block [jp, jp + b) (x_cur has bc entries, 0 if none).  Thread
+// (t-slot g, row i0 + l) covers t = g, g+16, ...; partial sums over the 16
+// t-slots are combined in a fixed order through LDS.
+__device__ void bwd_look(int i0, int bp, int bc, int nr, const double* Dp, const double* Cb, int b,
+                         const double* Y, int64_t jp, int64_t ldy, const double* xcur, double* xnext, double* B,
+                         int64_t ldb)
+{
+    __shared__ double ys[kDiagMax][kRhsGroup];
+    __shared__ double xs[kDiagMax][kRhsGroup];
+    __shared__ double red[16][16][kRhsGroup];
+    for (int e = threadIdx.x; e < kDiagMax * kRhsGroup; e += 256) {
+        const int r = e / kRhsGroup, c = e % kRhsGroup;
+        ys[r][c] = (r < bp && c < nr) ? Y[(jp + r) * ldy + c] : 0.0;
+        xs[r][c] = (r < bc && c < nr) ? xcur[e] : 0.0;
+    }
+    __syncthreads();
+    const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int i = i0 + l;
+    double acc[kRhsGroup];
+#pragma unroll
+    for (int c = 0; c < kRhsGroup; ++c) acc[c] = 0.0;
+    if (i < bp) {
+        double dv[kDiagMax / 16], cv[kDiagMax / 16];
+#pragma unroll
+        for (int m = 0; m < kDiagMax / 16; ++m) {
+            const int t = g + 16 * m;
+            dv[m] = (t >= i && t < bp) ? Dp[(int64_t)t * b + i] : 0.0;   // (Dinv^T)[i][t], Dinv lower
+            cv[m] = (Cb && t < bc) ? Cb[(int64_t)t * b + i] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < kRhsGroup; ++c) {
+            double t2 = 0.0;
+#pragma unroll
+            for (int m = 0; m < kDiagMax / 16; ++m) t2 += dv[m] * ys[g + 16 * m][c] - cv[m] * xs[g + 16 * m][c];
+            acc[c] = t2;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kRhsGroup; ++c) red[g][l][c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 16 && i0 + (int)threadIdx.x < bp) {
+        const int ii = i0 + threadIdx.x;
+        for (int c = 0; c < nr; ++c) {
+            double v = 0.0;
+            for (int gg = 0; gg < 16; ++gg) v += red[gg][threadIdx.x][c];
+            xnext[ii * kRhsGroup + c] = v;
+            B[(jp + ii) * ldb + c] = v;
+        }
     }
 }
 
+// Forward sweep, launch q (q = -1: z_0 only).  Workgroups < kLook form the
+// next block's z; the rest update the rows below the next block with z_q.
 __global__ void __launch_bounds__(256)
-trsv_bwd_first(int nr, int64_t j, int bq, const double* Dq, int b, const double* Y, int64_t ldy, double* zbuf,
-               double* B, int64_t ldb)
+trsv_fwd(int64_t n, int nr, int64_t q, int b, const double* L, int64_t ldl, const double* Dinv, const double* Cf,
+         double* Y, int64_t ldy, const double* zcur, double* znext, double* B, int64_t ldb)
 {
-    __shared__ double ys[kDiagMax][kRhsGroup];
-    __shared__ double red[4][64][kRhsGroup];
-    bwd_diag(j, bq, nr, Dq, b, Y, ldy, ys, red, zbuf, B, ldb);
+    const int64_t jn = (q + 1) * b;                       // next block
+    const int bn = (int)min((int64_t)b, n - jn);
+    const int bc = q >= 0 ? b : 0;                        // block q is full whenever a next block exists
+    if (blockIdx.x < kLook) {
+        fwd_look(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * b * b, q >= 0 ? Cf + (q + 1) * b * b : nullptr, b,
+                 Y, jn, ldy, zcur, znext, B, ldb);
+    } else {
+        __shared__ double z[kDiagMax][kRhsGroup];
+        for (int e = threadIdx.x; e < kDiagMax * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
+        __syncthreads();
+        const int64_t r0 = jn + bn + (int64_t)(blockIdx.x - kLook) * kRows;
+        fwd_rows(r0, min(n, r0 + kRows), q * b, b, nr, L, ldl, z, Y, ldy);
+    }
 }
 
-// Step q of the backward sweep: block [j, j+bq) solved (z_q in zcur); the
-// previous block is [jp, j) with jp = j - bqp.
+// Backward sweep, launch q (q = nblk: x_{nblk-1} only): workgroups < kLook
+// form x_{q-1}; the rest update the columns left of block q-1 with x_q.
 __global__ void __launch_bounds__(256)
-trsv_bwd_step(int nr, int64_t j, int bq, int64_t jp, int bqp, const double* L, int64_t ldl, const double* Dprev,
-              int b, double* Y, int64_t ldy, const double* zcur, double* znext, double* B, int64_t ldb)
+trsv_bwd(int64_t n, int nr, int64_t q, int64_t nblk, int b, const double* L, int64_t ldl, const double* Dinv,
+         const double* Cb, double* Y, int64_t ldy, const double* xcur, double* xnext, double* B, int64_t ldb)
 {
-    __shared__ double z[kDiagMax][kRhsGroup];
-    __shared__ double ys[kDiagMax][kRhsGroup];
-    __shared__ double red[4][64][kRhsGroup];
-    for (int e = threadIdx.x; e < bq * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
-    __syncthreads();
-    if (blockIdx.x == 0) {
-        for (int64_t r0 = jp; r0 < j; r0 += 64) bwd_cols(r0, min(j, r0 + 64), j, bq, nr, L, ldl, z, Y, ldy, red);
-        bwd_diag(jp, bqp, nr, Dprev, b, Y, ldy, ys, red, znext, B, ldb);
+    const int64_t jp = (q - 1) * b;                       // previous block
+    const int bp = (int)min((int64_t)b, n - jp);
+    const int bc = q < nblk ? (int)min((int64_t)b, n - q * b) : 0;
+    if (blockIdx.x < kLook) {
+        bwd_look(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * b * b, q < nblk ? Cb + (q - 1) * b * b : nullptr, b,
+                 Y, jp, ldy, xcur, xnext, B, ldb);
     } else {
-        const int64_t r0 = (int64_t)(blockIdx.x - 1) * 64;
-        if (r0 < jp) bwd_cols(r0, min(jp, r0 + 64), j, bq, nr, L, ldl, z, Y, ldy, red);
+        __shared__ double z[kDiagMax][kRhsGroup];
+        __shared__ double red[4][64][kRhsGroup];
+        for (int e = threadIdx.x; e < kDiagMax * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = xcur[e];
+        __syncthreads();
+        const int64_t r0 = (int64_t)(blockIdx.x - kLook) * 64;
+        if (r0 < jp) bwd_cols(r0, min(jp, r0 + 64), q * b, bc, nr, L, ldl, z, Y, ldy, red);
     }
 }
 
@@ -252,11 +286,72 @@ __global__ void __launch_bounds__(256) logdet_kernel(int64_t n, const double* L,
 
 int64_t trsm_workspace(int64_t n) { return (int64_t)kRhsGroup * n + 2 * kDiagMax * kRhsGroup; }
 
-hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
-                        const double* Dinv, int b, double* B, int64_t ldb, double* Y)
+hipError_t trsm_couplings(hipStream_t s, int trans, int64_t n, const double* L, int64_t ldl, const double* Dinv,
+                          int b, double* C)
 {
     const int64_t nblk = (n + b - 1) / b;
+    if (nblk < 2) return hipSuccess;
     const int64_t bb = (int64_t)b * b;
+    const int64_t last = nblk - 1;
+    const int bl = (int)(n - last * b);                   // rows of the last block
+    if (!trans) {
+        // Cf_q = Dinv_q L_{q,q-1}, q = 1 .. nblk-1 (the last one with bl rows)
+        const int64_t full = bl == b ? last : last - 1;   // full blocks among q = 1 .. last
+        if (full >= 1) {
+            GemmArgs g{};
+            g.M = b; g.N = b; g.K = b;
+            g.A = Dinv + bb; g.lda = b; g.a_lower = 1;
+            g.B = L + (int64_t)b * ldl; g.ldb = ldl;
+            g.C = C + bb; g.ldc = b;
+            g.kchunk = b;
+            g.bsA = bb; g.bsB = (int64_t)b * ldl + b; g.bsC = bb;
+            hipError_t e = gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g, 1, (int)full);
+            if (e != hipSuccess) return e;
+        }
+        if (bl != b) {
+            GemmArgs g{};
+            g.M = bl; g.N = b; g.K = bl;
+            g.A = Dinv + last * bb; g.lda = b; g.a_lower = 1;
+            g.B = L + last * b * ldl + (last - 1) * b; g.ldb = ldl;
+            g.C = C + last * bb; g.ldc = b;
+            g.kchunk = bl;
+            hipError_t e = gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g, 1, 1);
+            if (e != hipSuccess) return e;
+        }
+    } else {
+        // Cb_q = L_{q+1,q} Dinv_q, q = 0 .. nblk-2 (rows of block q+1)
+        const int64_t full = bl == b ? last : last - 1;   // q with a full block q+1
+        if (full >= 1) {
+            GemmArgs g{};
+            g.M = b; g.N = b; g.K = b;
+            g.A = L + (int64_t)b * ldl; g.lda = ldl;
+            g.B = Dinv; g.ldb = b;
+            g.C = C; g.ldc = b;
+            g.kchunk = b;
+            g.bsA = (int64_t)b * ldl + b; g.bsB = bb; g.bsC = bb;
+            hipError_t e = gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g, 1, (int)full);
+            if (e != hipSuccess) return e;
+        }
+        if (bl != b) {
+            const int64_t q = last - 1;
+            GemmArgs g{};
+            g.M = bl; g.N = b; g.K = b;
+            g.A = L + last * b * ldl + q * b; g.lda = ldl;
+            g.B = Dinv + q * bb; g.ldb = b;
+            g.C = C + q * bb; g.ldc = b;
+            g.kchunk = b;
+            hipError_t e = gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g, 1, 1);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
+                        const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb, double* Y)
+{
+    if (b != kDiagMax) return hipErrorInvalidValue;
+    const int64_t nblk = (n + b - 1) / b;
     double* zb = Y + (int64_t)kRhsGroup * n;            // two z slots
     auto zslot = [&](int64_t q) { return zb + (q & 1) * kDiagMax * kRhsGroup; };
     for (int64_t c0 = 0; c0 < nrhs; c0 += kRhsGroup) {
@@ -265,27 +360,19 @@ hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const
         hipLaunchKernelGGL(copy_cols, dim3((unsigned)((n * nr + 255) / 256)), dim3(256), 0, s, n, nr, Bc, ldb, Y,
                            (int64_t)kRhsGroup);
         if (!trans) {
-            hipLaunchKernelGGL(trsv_fwd_first, dim3(1), dim3(256), 0, s, nr, (int)std::min<int64_t>(b, n), Dinv, b,
-                               Y, (int64_t)kRhsGroup, zslot(0), Bc, ldb);
-            for (int64_t q = 0; q + 1 < nblk; ++q) {
-                const int64_t j = q * b;
-                const int bq = b;
-                const int bq1 = (int)std::min<int64_t>(b, n - j - b);
-                const int64_t rest = n - (j + bq + bq1);
-                const int64_t blocks = 1 + std::max<int64_t>(0, (rest + kRows - 1) / kRows);
-                hipLaunchKernelGGL(trsv_fwd_step, dim3((unsigned)blocks), dim3(256), 0, s, n, nr, j, bq, bq1, L, ldl,
-                                   Dinv + (q + 1) * bb, b, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
+            for (int64_t q = -1; q + 1 < nblk; ++q) {
+                const int64_t jn = (q + 1) * b;
+                const int64_t rest = n - std::min(n, jn + b);
+                const int64_t blocks = kLook + (q >= 0 ? (rest + kRows - 1) / kRows : 0);
+                hipLaunchKernelGGL(trsv_fwd, dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, b, L, ldl, Dinv, Cpl,
+                                   Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
             }
         } else {
-            const int64_t jl = (nblk - 1) * b;
-            hipLaunchKernelGGL(trsv_bwd_first, dim3(1), dim3(256), 0, s, nr, jl, (int)(n - jl), Dinv + (nblk - 1) * bb,
-                               b, Y, (int64_t)kRhsGroup, zslot(nblk - 1), Bc, ldb);
-            for (int64_t q = nblk - 1; q >= 1; --q) {
-                const int64_t j = q * b, jp = j - b;
-                const int bq = (int)std::min<int64_t>(b, n - j);
-                const int64_t blocks = 1 + (jp + 63) / 64;
-                hipLaunchKernelGGL(trsv_bwd_step, dim3((unsigned)blocks), dim3(256), 0, s, nr, j, bq, jp, b, L, ldl,
-                                   Dinv + (q - 1) * bb, b, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
+            for (int64_t q = nblk; q >= 1; --q) {
+                const int64_t jp = (q - 1) * b;
+                const int64_t blocks = kLook + (q < nblk ? (jp + 63) / 64 : 0);
+                hipLaunchKernelGGL(trsv_bwd, dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, nblk, b, L, ldl, Dinv,
+                                   Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
             }
         }
         hipError_t e = hipGetLastError();
