@@ -198,9 +198,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     // the same point (there is room for them in a 64 x 64 tile) and the
     // epilogue writes C - A B without a read of its own
     constexpr bool kPre = EPI == EPI_SUB && sizeof(TI) == 4 && FM * FN <= 4;
+    // FP32 subtract, larger tiles: the same FP64 copy of C is read just
+    // before the last k-chunk, when the staging registers are free, so its
+    // latency overlaps that chunk's MFMAs
+    constexpr bool kLate = EPI == EPI_SUB && sizeof(TI) == 4 && !kPre;
+    constexpr bool kC = kPre || kLate;
     typedef typename Mfma<TI>::acc_t acc_t;
     acc_t acc[FM][FN];
-    double cpre[kPre ? FM : 1][kPre ? FN : 1][4];
+    double cpre[kC ? FM : 1][kC ? FN : 1][4];
     const int lr = lane >> 4, lc = lane & 15;
     auto load_c = [&]() {
         const auto rc = operand_rsrc(g.C + m0 * g.ldc + n0);
@@ -216,7 +221,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                     const int col = wn * WTN + j * 16 + lc;
                     const bool in = (m0 + row < g.M) & (n0 + col < g.N) & !(lowc & (n0 + col > m0 + row));
                     const double cv = buffer_ld<double>(rc, in ? (uint32_t)row * ldc8 + (uint32_t)col * 8u : kOffOut);
-                    if (kPre) cpre[kPre ? i : 0][kPre ? j : 0][r] = cv;
+                    if (kC) cpre[kC ? i : 0][kC ? j : 0][r] = cv;
                     else acc[i][j][r] = (typename Mfma<TI>::elem_t)cv;
                 }
     };
@@ -370,9 +375,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
             store(cur ^ 1);
             __syncthreads();
         }
+        if (kLate) load_c();
         compute((int)(c & 1), RegTag());
         __syncthreads();
-    } else if (kFold || kPre) {
+    } else if (kFold || kC) {
         load_c();
     }
 
@@ -390,7 +396,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                 const double v = (double)acc[i][j][r];
                 if (EPI == EPI_SUB) {
                     if (kFold) g.C[row * g.ldc + col] = v;
-                    else if (kPre) g.C[row * g.ldc + col] = cpre[kPre ? i : 0][kPre ? j : 0][r] - v;
+                    else if (kC) g.C[row * g.ldc + col] = cpre[kC ? i : 0][kC ? j : 0][r] - v;
                     else g.C[row * g.ldc + col] -= v;
                 } else if (EPI == EPI_STORE) {
                     g.C[row * g.ldc + col] = v;
