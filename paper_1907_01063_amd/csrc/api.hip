@@ -200,6 +200,15 @@ void splitk_plan(int64_t tiles, int64_t K, int max_splits, int* splits, int64_t*
     *chunk = c;
 }
 
+// Skinny products on the factor's critical path (the narrow updates, whose C
+// is disjoint from their operands): 64 x 64 tiles when 128 x 128 tiles would
+// leave most of the 2 x 256 workgroup slots empty.
+TileCfg skinny_tile(int64_t M, int64_t N)
+{
+    const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128);
+    return t128 < 256 ? TILE_64 : TILE_128;
+}
+
 GemmArgs gemm_args(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
                    int64_t ldb, double* C, int64_t ldc)
 {
@@ -407,10 +416,11 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
                     pg.Cf = Pf + (kh + bh - k) * B + h0;
                     pg.ldcf = B;
                 }
+                // in place: one 128-wide tile column, so no tile writes columns another reads
                 GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_STORE, false, pg, 1));
             }
-            if (h0 + bh < kB) {   // the next half of this outer block
-                const int nh = std::min(ib, kB - h0 - bh);
+            if (h0 + bh < kB) {   // the rest of this outer block
+                const int nh = kB - h0 - bh;
                 const double dnh = (double)nh;
                 Traced tr(h, GPC_K_TRAILING_NARROW, 2.0 * dbh * ((dm - dnh) * dnh + dnh * (dnh + 1.0) / 2.0),
                           8.0 * (2.0 * dm * dnh + dm * dbh));
@@ -418,11 +428,11 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
                     const float* Pr = Pf + (kh + bh - k) * B + h0;
                     GemmArgs ng = gemm_args(m, nh, bh, Pr, B, Pr, B, P + bh, lda);
                     ng.c_lower = 1;
-                    GPC_HIP(h, gemm_f32in(s, TILE_128, false, true, EPI_SUB, false, ng, 1));
+                    GPC_HIP(h, gemm_f32in(s, skinny_tile(m, nh), false, true, EPI_SUB, false, ng, 1));
                 } else {
                     GemmArgs ng = gemm_args(m, nh, bh, P, lda, P, lda, P + bh, lda);
                     ng.c_lower = 1;
-                    GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_SUB, false, ng, 1));
+                    GPC_HIP(h, gemm_f64(s, skinny_tile(m, nh), false, true, EPI_SUB, false, ng, 1));
                 }
             }
         }
@@ -461,11 +471,11 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
             if (mixed) {
                 GemmArgs ng = gemm_args(m2, nB, kB, Pr, B, Pr, B, Cn, lda);
                 ng.c_lower = 1;
-                GPC_HIP(h, gemm_f32in(s, TILE_128, false, true, EPI_SUB, false, ng, 1));
+                GPC_HIP(h, gemm_f32in(s, skinny_tile(m2, nB), false, true, EPI_SUB, false, ng, 1));
             } else {
                 GemmArgs ng = gemm_args(m2, nB, kB, Pd, lda, Pd, lda, Cn, lda);
                 ng.c_lower = 1;
-                GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_SUB, false, ng, 1));
+                GPC_HIP(h, gemm_f64(s, skinny_tile(m2, nB), false, true, EPI_SUB, false, ng, 1));
             }
         }
         if (!la) {

@@ -60,11 +60,14 @@ __device__ void invert_in_lds(double* S, double* xd, int kb)
     __syncthreads();
 }
 
+// NA: 16-row groups held per thread (blocks up to 16 NA; smaller blocks take
+// the smaller instance, whose per-column work is proportionally smaller).
+template <int NA>
 __global__ void __launch_bounds__(256)
 potrf_diag_kernel(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info, int64_t col0)
 {
-    __shared__ double colbuf[2 * kDiagMax], rowbuf[2 * kDiagMax], piv[4], rls[kDiagMax];
-    diag_factor_inverse<kDiagMax / 16>(kb, A, lda, Linv, ldi, info, col0, colbuf, rowbuf, piv, rls);
+    __shared__ double colbuf[2 * 16 * NA], rowbuf[2 * 16 * NA], piv[4], rls[16 * NA];
+    diag_factor_inverse<NA>(kb, A, lda, Linv, ldi, info, col0, colbuf, rowbuf, piv, rls);
 }
 
 __global__ void __launch_bounds__(256)
@@ -141,7 +144,13 @@ hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Lin
 {
     if (kb <= 0) return hipSuccess;
     if (kb > kDiagMax || lda > (int64_t(1) << 20)) return hipErrorInvalidValue;   // 31-bit row-band offsets
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
+    if (kb <= 32)
+        hipLaunchKernelGGL(potrf_diag_kernel<2>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
+    else if (kb <= 64)
+        hipLaunchKernelGGL(potrf_diag_kernel<4>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
+    else
+        hipLaunchKernelGGL(potrf_diag_kernel<kDiagMax / 16>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info,
+                           col0);
     return hipGetLastError();
 }
 

@@ -95,6 +95,8 @@ hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, b
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, false, EPI_SUB, false)
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, false, EPI_PARTIAL, false)
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_PARTIAL, false)
+    // skinny narrow update (more, smaller tiles)
+    GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, false, true, EPI_SUB, false)
     // diagonal-block reverse step
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_SYMLOW, false)
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, false, false, EPI_STORE, false)
@@ -111,6 +113,7 @@ hipError_t gemm_f32in(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi,
     GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, false, false, EPI_SUB, false)
     GPC_GEMM_CASE(float, TILE_128, 128, 128, 32, true, false, EPI_PARTIAL, false)
     GPC_GEMM_CASE(float, TILE_64, 64, 64, 32, true, false, EPI_PARTIAL, false)
+    GPC_GEMM_CASE(float, TILE_64, 64, 64, 32, false, true, EPI_SUB, false)
     return hipErrorInvalidValue;
 }
 
