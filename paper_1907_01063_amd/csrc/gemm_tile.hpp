@@ -250,17 +250,28 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     const int64_t nchunk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
     // LDS layouts.  Register path: both operands k-major, sA[k][m] and
     // sB[k][n] (pitch BM + PAD).  Direct path (16-byte lane loads that go
-    // straight from memory into LDS): a KM or KN operand keeps the k-major
-    // layout, one 1 KB k-row per wave load; an MK or NK operand is stored
-    // row-major, its BK = 16 k values (128 B) per row, with the row's 16-byte
-    // pairs permuted by (row >> 1) & 7 so that the 16 rows one MFMA operand
-    // fetch touches fall into distinct banks.  Direct loads carry no sign
-    // flip, so the subtracting form negates A at the fragment read instead.
-    const int sw = (lc >> 1) & 7;     // pair permutation of the rows this lane reads
+    // straight from memory into LDS, no register staging):
+    //  - an MK or NK operand is stored row-major, BK k values (128 B) per row,
+    //    with the row's 16-byte groups permuted by (row >> 1) & 7, so that the
+    //    16 rows one MFMA operand fetch touches fall into distinct banks;
+    //  - a KM or KN operand stays k-major: FP64 k-rows are 1 KB (one wave
+    //    load each, padded pitch as in the register path); FP32 k-rows are
+    //    512 B, stored unpadded two per wave load, with the 16-byte groups of
+    //    row k permuted by (k & 3) << 2 (the four k-rows of one fetch then
+    //    sit 64 B apart in the banks).
+    // Direct loads carry no sign flip, so the subtracting form negates A at
+    // the fragment read instead.
+    constexpr int VE = 16 / (int)sizeof(TI);   // elements per 16-byte group
+    const int sw = (lc >> 1) & 7;             // group permutation of the MK/NK rows this lane reads
+    auto frag = [&](const TI* buf, int k, int r, bool kmajor_padded, bool rowmajor) -> TI {
+        if (rowmajor) return buf[r * BK + (((k / VE) ^ sw) * VE) + (k % VE)];
+        if (kmajor_padded) return buf[k * (BM + PAD) + r];
+        return buf[k * BM + (((r >> 2) ^ ((k & 3) << 2)) << 2) + (r & 3)];   // FP32 k-major, permuted
+    };
     auto compute = [&](int cur, auto dir_tag) {
         constexpr bool dir = decltype(dir_tag)::value;
-        const TI* rowA = &sA(cur, 0)[0];
-        const TI* rowB = &sB(cur, 0)[0];
+        const TI* bufA = &sA(cur, 0)[0];
+        const TI* bufB = &sB(cur, 0)[0];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int k = kk + lr;
@@ -268,11 +279,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
                 const int r = wm * WTM + i * 16 + lc;
-                if (dir && !AKM) {
-                    const TI x = rowA[r * BK + (((k >> 1) ^ sw) << 1) + (k & 1)];
+                if (dir) {
+                    const TI x = frag(bufA, k, r, AKM && sizeof(TI) == 8, !AKM);
                     a[i] = kFold ? -x : x;
-                } else if (dir) {
-                    a[i] = kFold ? -sA(cur, k)[r] : sA(cur, k)[r];
                 } else {
                     a[i] = sA(cur, k)[r];
                 }
@@ -280,7 +289,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 const int c = wn * WTN + j * 16 + lc;
-                b[j] = (dir && BNK) ? rowB[c * BK + (((k >> 1) ^ sw) << 1) + (k & 1)] : sB(cur, k)[c];
+                b[j] = dir ? frag(bufB, k, c, !BNK && sizeof(TI) == 8, BNK) : sB(cur, k)[c];
             }
 #pragma unroll
             for (int i = 0; i < FM; ++i)
@@ -292,56 +301,86 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     typedef std::integral_constant<bool, true> DirectTag;
     typedef std::integral_constant<bool, false> RegTag;
 
-    // direct path: FP64 128 x 128 tiles of 8 waves, 16-byte aligned rows,
-    // no per-element masks; KM/KN rows must be whole (16-byte pairs inside
-    // the operand), MK/NK k ranges even (pairs never straddle the k end)
-    constexpr bool kDirectShape = sizeof(TI) == 8 && sizeof(TG) == 8 && BM == 128 && BN == 128 && NT == 512 && BK == 16;
+    // direct path: 128 x 128 tiles of 8 waves whose k-chunk is 128 B per
+    // row-major row, 16-byte aligned rows, no per-element masks; k-major
+    // operands must cover whole tile rows (16-byte groups inside the operand,
+    // FP32 head rows in pairs), row-major k ranges a whole number of groups
+    // (groups never straddle the k end)
+    constexpr bool kDirectShape =
+        sizeof(TI) == sizeof(TG) && BM == 128 && BN == 128 && NT == 512 && BK * sizeof(TI) == 128;
     bool direct = false;
     if (kDirectShape && nchunk > 0 && g.a_lower == 0) {
-        const bool evenk = ((kend - kbeg) & 1) == 0;
-        const bool okA = ((uintptr_t)Ap & 15) == 0 && (g.lda & 1) == 0 &&
-                         (AKM ? (m0 + BM <= g.M && (g.head_k == 0 || (((uintptr_t)Hp & 15) == 0 && (g.ldah & 1) == 0)))
-                              : evenk);
-        const bool okB = ((uintptr_t)Bp & 15) == 0 && (g.ldb & 1) == 0 && (BNK ? evenk : n0 + BN <= g.N);
+        const bool kgroups = ((kend - kbeg) % VE) == 0;
+        const bool okA = ((uintptr_t)Ap & 15) == 0 && (g.lda % VE) == 0 &&
+                         (AKM ? (m0 + BM <= g.M &&
+                                 (g.head_k == 0 || (((uintptr_t)Hp & 15) == 0 && (g.ldah % VE) == 0 &&
+                                                    (sizeof(TI) == 8 || (g.head_k & 1) == 0))))
+                              : kgroups);
+        const bool okB = ((uintptr_t)Bp & 15) == 0 && (g.ldb % VE) == 0 && (BNK ? kgroups : n0 + BN <= g.N);
         direct = okA && okB;
     }
     if (kDirectShape && direct) {
         typedef __attribute__((address_space(3))) void lds_void;
         // MK / NK: wave w fills rows 8w .. 8w+7 and 64+8w .. 64+8w+7; lane l
-        // takes row 8w + l/8 (+64) and stores its pair l%8, which holds the
-        // operand's k pair (l%8) ^ ((row >> 1) & 7)
+        // takes row 8w + l/8 (+64) and stores its group l%8, which holds the
+        // operand's k group (l%8) ^ ((row >> 1) & 7)
         const int rr = 8 * wave + (lane >> 3);
         const int pp = (lane & 7) ^ ((rr >> 1) & 7);    // same for rr + 64
+        // FP32 KM / KN: wave w fills k-rows 2w, 2w+1 and 16+2w, 16+2w+1; lane l
+        // takes k-row 2w + l/32 (+16) and stores group l%32, which holds the
+        // operand's group (l%32) ^ ((k & 3) << 2)
+        const int kq = 2 * wave + (lane >> 5);
+        const int gq = (lane & 31) ^ ((kq & 3) << 2);  // same for kq + 16
         auto issue = [&](int64_t k0, int buf) {
             const int krem = (int)(kend - k0);
             TI* dA = &sA(buf, 0)[0];
             TI* dB = &sB(buf, 0)[0];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                if (AKM) {
+                if (AKM && sizeof(TI) == 8) {
                     const int kk = wave + 8 * h;
                     const int64_t gk = k0 + kk;
                     const TG* base = gk < g.head_k ? Hp + gk * g.ldah + m0 : Ap + (gk - g.head_k) * g.lda + m0;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(base), (lds_void*)&sA(buf, kk)[0], 16,
                                                              kk < krem ? (uint32_t)lane * 16u : kOffOut, 0, 0, 0);
+                } else if (AKM) {
+                    const int kr = 2 * wave + 16 * h;          // first k-row of this load (even)
+                    const int64_t gk = k0 + kr;                 // k-rows gk, gk+1 come from the same segment
+                    const bool head = gk < g.head_k;
+                    const TG* base = head ? Hp + gk * g.ldah + m0 : Ap + (gk - g.head_k) * g.lda + m0;
+                    const int64_t ld = head ? g.ldah : g.lda;
+                    const int kl = lane >> 5;                   // 0 or 1
+                    const uint32_t off =
+                        kr + kl < krem ? (uint32_t)(kl * ld + 4 * gq) * (uint32_t)sizeof(TG) : kOffOut;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(base), (lds_void*)(dA + kr * BM), 16, off,
+                                                             0, 0, 0);
                 } else {
                     const int r = rr + 64 * h;
-                    const uint32_t off = (m0 + r < g.M) & (2 * pp < krem)
-                                             ? (uint32_t)(r * g.lda + 2 * pp) * (uint32_t)sizeof(TG) : kOffOut;
+                    const uint32_t off = (m0 + r < g.M) & (VE * pp < krem)
+                                             ? (uint32_t)(r * g.lda + VE * pp) * (uint32_t)sizeof(TG) : kOffOut;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Ap + m0 * g.lda + k0),
-                                                             (lds_void*)(dA + (8 * wave + 64 * h) * BK), 16, off, 0, 0, 0);
+                                                             (lds_void*)(dA + (8 * wave + 64 * h) * BK), 16, off, 0, 0,
+                                                             0);
                 }
-                if (!BNK) {
+                if (!BNK && sizeof(TI) == 8) {
                     const int kk = wave + 8 * h;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Bp + (k0 + kk) * g.ldb + n0),
                                                              (lds_void*)&sB(buf, kk)[0], 16,
                                                              kk < krem ? (uint32_t)lane * 16u : kOffOut, 0, 0, 0);
+                } else if (!BNK) {
+                    const int kr = 2 * wave + 16 * h;
+                    const int kl = lane >> 5;
+                    const uint32_t off =
+                        kr + kl < krem ? (uint32_t)(kl * g.ldb + 4 * gq) * (uint32_t)sizeof(TG) : kOffOut;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Bp + (k0 + kr) * g.ldb + n0),
+                                                             (lds_void*)(dB + kr * BN), 16, off, 0, 0, 0);
                 } else {
                     const int r = rr + 64 * h;
-                    const uint32_t off = (n0 + r < g.N) & (2 * pp < krem)
-                                             ? (uint32_t)(r * g.ldb + 2 * pp) * (uint32_t)sizeof(TG) : kOffOut;
+                    const uint32_t off = (n0 + r < g.N) & (VE * pp < krem)
+                                             ? (uint32_t)(r * g.ldb + VE * pp) * (uint32_t)sizeof(TG) : kOffOut;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Bp + n0 * g.ldb + k0),
-                                                             (lds_void*)(dB + (8 * wave + 64 * h) * BK), 16, off, 0, 0, 0);
+                                                             (lds_void*)(dB + (8 * wave + 64 * h) * BK), 16, off, 0, 0,
+                                                             0);
                 }
             }
         };
@@ -357,6 +396,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
             __builtin_amdgcn_s_waitcnt(0x0F70);
             __syncthreads();
         }
+        if (kLate) load_c();
         compute((int)(c & 1), DirectTag());
         __syncthreads();
     } else if (nchunk > 0) {
