@@ -76,6 +76,10 @@ __device__ void diag_factor_inverse(int kb, double* A, int64_t lda, double* Linv
             const int i = ty + 16 * a, c = tx + 16 * b;
             E[a][b] = (i < kb && c <= i) ? A[i * lda + c] : 0.0;
         }
+    // wait for the block's loads here, once: otherwise the wait for them sits
+    // inside the column loop, where it also waits for every store of L issued
+    // by the previous columns
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     // byte offset of row ty + 16a of A
     uint32_t rowoff[NA];
 #pragma unroll
@@ -218,6 +222,10 @@ __device__ void diag_factor_inverse_g4(int kb, double* A, int64_t lda, double* L
             const int i = ty + 16 * a, c = tx + 16 * b;
             E[a][b] = (i < kb && c <= i) ? A[i * lda + c] : 0.0;
         }
+    // wait for the block's loads here, once: otherwise the wait for them sits
+    // inside the column loop, where it also waits for every store of L issued
+    // by the previous columns
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     // byte offset of row ty + 16a of A
     uint32_t rowoff[NA];
 #pragma unroll
