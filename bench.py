@@ -94,10 +94,12 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--lookahead", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=5120)
+    ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--gp-evals", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--serial-classes", action="store_true",
+                    help="also trace one step with lookahead off (per-class kernel times, each kernel alone)")
     ap.add_argument("--headline-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -137,6 +139,17 @@ def main():
         H.adjoint(L, Lb)
 
     ms = timed(step64, args.steps, args.warmup)
+    tr_timed = None
+    if not args.no_trace:
+        # the same number of steps again, same schedule, with the library's
+        # launch trace on: every kernel launch bracketed by HIP events on the
+        # stream it runs on (the events cost about 4 % of a step, so the
+        # step time above is taken without them)
+        H.trace_reset()
+        H.trace_enable(True)
+        timed(step64, args.steps, 0)
+        tr_timed = H.trace_read()
+        H.trace_enable(False)
     if int(info.item()) != 0:
         raise SystemExit(f"factor reported info={int(info.item())}")
     value = F / (ms * 1e-3) / 1e9
@@ -149,21 +162,25 @@ def main():
 
     roof = None
     if not args.no_trace:
-        # traced pass in the serial schedule (lookahead off): every kernel then
-        # runs alone, so its event-measured duration is its own
-        H.set_options(lookahead=0)
-        H.trace_enable(True)
-        H.trace_reset()
-        step64()
-        tr = H.trace_read()
-        H.trace_enable(False)
-        H.set_options(lookahead=args.lookahead)
+        tr = tr_timed
         # roofline kernel: the adjoint's left update Bbar -= Cbar R, the largest
-        # MFMA contraction that runs alone on its stream (the trailing update
-        # overlaps the panel work, which inflates its event-measured duration)
+        # MFMA contraction of the step (its launches overlap the diagonal chain
+        # of the next block on the other stream, as in every timed step)
         dom = "adj_left_update"
         cnt, kms, kfl, kby = tr[dom]
         achieved = kfl / (kms * 1e-3) / 1e12
+        serial = None
+        if args.serial_classes:
+            # one more step with lookahead off: every kernel then runs alone
+            H.set_options(lookahead=0)
+            H.trace_reset()
+            H.trace_enable(True)
+            step64()
+            torch.cuda.synchronize()
+            serial = {k: round(v[1], 3) for k, v in H.trace_read().items() if v[0]}
+            H.trace_enable(False)
+            H.set_options(lookahead=args.lookahead)
+            log(f"serial classes (ms per step): {serial}")
         # wall clock of each phase of the step (main stream), for the breakdown
         def phase(fn, reps=2):
             return round(timed(fn, reps, 0), 3)
@@ -175,12 +192,15 @@ def main():
         phases["factor"] = round(phases["factor"] - phases["copy_A"], 3)
         phases["adjoint"] = round(phases["adjoint"] - phases["copy_A"], 3)
         log(f"phases (ms, copies of the inputs removed): {phases}")
-        roof = {"bound": "mfma", "kernel": dom, "schedule": "serial (lookahead off) traced pass",
+        roof = {"bound": "mfma", "kernel": dom,
+                "schedule": f"{args.steps} traced steps after the timed ones (lookahead {args.lookahead}), HIP events per launch",
                 "launches": cnt, "achieved": round(achieved, 3),
                 "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
                 "traffic": measured_traffic(dom), "avg_launch_ms": round(kms / max(cnt, 1), 4),
+                "algorithmic_flops_per_launch": round(kfl / max(cnt, 1)),
                 "algorithmic_bytes_per_launch": round(kby / max(cnt, 1)),
-                "classes_ms": {k: round(v[1], 3) for k, v in tr.items() if v[0]}, "phases_ms": phases}
+                "classes_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in tr.items() if v[0]},
+                "serial_classes_ms": serial, "phases_ms": phases}
         log(f"trace: {json.dumps(roof)}")
 
     cfg = {"workload": f"matern32-2d-n{n} factor+solves+logdet+adjoint", "n": n, "form": "fp64",
@@ -204,22 +224,19 @@ def main():
             Hm.adjoint(Lm, Lbm)
 
         msm = timed(stepmix, args.steps, args.warmup)
+        trm = None
+        if not args.no_trace:
+            Hm.trace_reset()
+            Hm.trace_enable(True)
+            timed(stepmix, args.steps, 0)
+            trm = {k: round(v[1] / args.steps, 3) for k, v in Hm.trace_read().items() if v[0]}
+            Hm.trace_enable(False)
         cpm = timed(lambda: Lm.copy_(A0), 2, 0)
         phm = {"factor": round(timed(lambda: (Lm.copy_(A0), Hm.factor(Lm, info)), 2, 0) - cpm, 3),
                "refined_solve": round(timed(lambda: Hm.solve_refined(A0, Lm, y0, x=xr, check=False), 2, 0), 3),
                "adjoint": round(timed(lambda: (Lbm.copy_(Lb0), Hm.adjoint(Lm, Lbm)), 2, 0) - cpm, 3)}
         log(f"mixed phases (ms): {phm}")
-        trm = None
-        if not args.no_trace:
-            # per-class kernel time of the mixed step, serial schedule (as for FP64)
-            Hm.set_options(lookahead=0)
-            Hm.trace_enable(True)
-            Hm.trace_reset()
-            stepmix()
-            trm = {k: round(v[1], 3) for k, v in Hm.trace_read().items() if v[0]}
-            Hm.trace_enable(False)
-            Hm.set_options(lookahead=args.lookahead)
-            log(f"mixed trace classes (ms): {trm}")
+        log(f"mixed trace classes (ms per step, traced steps): {trm}")
         it, etam = int(out["it"].item()), float(out["eta"].item())
         eL = (torch.linalg.norm(Lm - L) / torch.linalg.norm(L)).item()
         eA = (torch.linalg.norm(Lbm - Lb) / torch.linalg.norm(Lb)).item()
@@ -229,7 +246,7 @@ def main():
             f"err vs fp64: L {eL:.2e} Abar {eA:.2e} alpha {ea:.2e}")
         cfg["mixed"] = {"value": round(vm, 2), "unit": "GFLOP/s", "ms_per_step": round(msm, 3),
                         "speedup_vs_fp64": round(ms / msm, 3), "refine_iters": it, "refined_eta_inf": etam,
-                        "phases_ms": phm, "classes_ms": trm,
+                        "phases_ms": phm, "classes_ms_per_step": trm,
                         "err_vs_fp64_path": {"L": eL, "Abar": eA, "alpha": ea},
                         "step": "factor (FP32 trailing updates) + FP64-refined solve + log-det + adjoint"}
         del Lm, Lbm, Hm
