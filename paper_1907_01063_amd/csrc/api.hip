@@ -203,6 +203,10 @@ void splitk_plan(int64_t tiles, int64_t K, int max_splits, int* splits, int64_t*
 // Skinny products on the factor's critical path (the narrow updates, whose C
 // is disjoint from their operands): 64 x 64 tiles when 128 x 128 tiles would
 // leave most of the 2 x 256 workgroup slots empty.
+// Block size of the solve sweeps: 256 halves the number of dependent steps
+// once the matrix holds a few such blocks.
+int solve_block(int64_t n) { return n >= 512 ? 2 * kDiagMax : kDiagMax; }
+
 TileCfg skinny_tile(int64_t M, int64_t N)
 {
     const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128);
@@ -222,6 +226,41 @@ GemmArgs gemm_args(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, 
 }
 
 }  // namespace
+
+// 256-blocks D = [[D1, 0], [D21, D2]]: D^-1 = [[X1, 0], [-X2 D21 X1, X2]],
+// X1 and X2 from the 128-block inverse kernel, the corner by two products.
+hipError_t gpc::diag_block_inverses(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl, double* Dinv,
+                                    double* Tmp)
+{
+    if (b <= kDiagMax) return trtri_diag_batched(s, n, b, L, ldl, Dinv);
+    if (b != 2 * kDiagMax) return hipErrorInvalidValue;
+    const int hb = kDiagMax;
+    const int64_t nblk = (n + b - 1) / b, bb = (int64_t)b * b;
+    hipError_t e = fill_f64(s, nblk * bb, Dinv, 0.0);
+    if (e == hipSuccess) e = trtri_diag_pairs(s, n, L, ldl, Dinv);
+    if (e == hipSuccess) e = fill_f64(s, nblk * (int64_t)hb * hb, Tmp, 0.0);
+    const int64_t nfull = n / b;
+    auto compose = [&](int64_t p0, int64_t cnt, int64_t m2) -> hipError_t {
+        if (cnt <= 0 || m2 <= 0) return hipSuccess;
+        const double* L21 = L + (p0 * b + hb) * ldl + p0 * b;
+        double* X1 = Dinv + p0 * bb;
+        double* T0 = Tmp + p0 * (int64_t)hb * hb;
+        GemmArgs g1 = gemm_args(m2, hb, hb, L21, ldl, X1, b, T0, hb);   // T0 = -D21 X1
+        g1.bsA = (int64_t)b * ldl + b;
+        g1.bsB = bb;
+        g1.bsC = (int64_t)hb * hb;
+        hipError_t r = gemm_f64(s, TILE_128, false, false, EPI_SUB, false, g1, 1, (int)cnt);
+        if (r != hipSuccess) return r;
+        GemmArgs g2 = gemm_args(m2, hb, m2, X1 + (int64_t)hb * b + hb, b, T0, hb, X1 + (int64_t)hb * b, b);
+        g2.bsA = bb;
+        g2.bsB = (int64_t)hb * hb;
+        g2.bsC = bb;
+        return gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g2, 1, (int)cnt);
+    };
+    if (e == hipSuccess) e = compose(0, nfull, hb);
+    if (e == hipSuccess) e = compose(nfull, nblk - nfull, n - nfull * b - hb);   // ragged last block's second half
+    return e;
+}
 
 extern "C" {
 
@@ -588,7 +627,8 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         }
     }
     const size_t bb = (size_t)b * b;
-    const size_t n_dinv = (size_t)nblk * bb, n_pd = (size_t)kMaxSd * bb;
+    const size_t n_dinv = (size_t)nblk * bb;
+    const size_t n_pd = std::max((size_t)kMaxSd * bb, (size_t)nblk * kDiagMax * kDiagMax);
     const size_t n_dbl = n_dinv + n_pd + 5 * bb + (size_t)prn_elems + (size_t)prb_elems;
     // mixed: FP32 copies of the strict lower triangle of L, and (two each) of
     // the current Cbar panel and of M: the FP32 operands of the updates
@@ -612,38 +652,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     {
         const double db = (double)b;
         Traced t(h, GPC_K_DIAG_INVERSE, (double)nblk * db * db * db / 3.0, 8.0 * 2.0 * (double)nblk * db * db);
-        if (b <= kDiagMax) {
-            GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
-        } else {
-            // 256-blocks D = [[D1, 0], [D21, D2]]: D^-1 = [[X1, 0], [-X2 D21 X1, X2]]
-            const int hb = kDiagMax;
-            GPC_HIP(h, fill_f64(s, (int64_t)n_dinv, Dinv, 0.0));
-            GPC_HIP(h, trtri_diag_pairs(s, n, L, ldl, Dinv));
-            double* Tmp = Pd;   // nblk x 128 x 128, free until the sweep
-            GPC_HIP(h, fill_f64(s, nblk * (int64_t)hb * hb, Tmp, 0.0));
-            const int64_t nfull = n / b;
-            auto compose = [&](int64_t p0, int64_t cnt, int64_t m2) -> gpc_status {
-                if (cnt <= 0 || m2 <= 0) return GPC_OK;
-                const double* L21 = L + (p0 * b + hb) * ldl + p0 * b;
-                double* X1 = Dinv + p0 * (int64_t)bb;
-                double* T0 = Tmp + p0 * (int64_t)hb * hb;
-                GemmArgs g1 = gemm_args(m2, hb, hb, L21, ldl, X1, b, T0, hb);
-                g1.bsA = (int64_t)b * ldl + b;
-                g1.bsB = (int64_t)bb;
-                g1.bsC = (int64_t)hb * hb;
-                GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_SUB, false, g1, 1, (int)cnt));
-                GemmArgs g2 = gemm_args(m2, hb, m2, X1 + (int64_t)hb * b + hb, b, T0, hb, X1 + (int64_t)hb * b, b);
-                g2.bsA = (int64_t)bb;
-                g2.bsB = (int64_t)hb * hb;
-                g2.bsC = (int64_t)bb;
-                GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g2, 1, (int)cnt));
-                return GPC_OK;
-            };
-            st = compose(0, nfull, hb);
-            if (st != GPC_OK) return st;
-            st = compose(nfull, nblk - nfull, n - nfull * b - hb);   // ragged last block, if it has a second half
-            if (st != GPC_OK) return st;
-        }
+        GPC_HIP(h, diag_block_inverses(s, n, b, L, ldl, Dinv, Pd));   // Pd is free until the sweep
     }
     hipStream_t s2 = s;
     if (la) {
@@ -799,7 +808,7 @@ gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const
         return GPC_ERR_ARG;
     if (n == 0 || nrhs == 0) return GPC_OK;
     hipStream_t s = h->stream;
-    const int b = kDiagMax;   // solves sweep 128-blocks
+    const int b = solve_block(n);
     const int64_t nblk = (n + b - 1) / b;
     const size_t n_dinv = (size_t)nblk * b * b;
     gpc_status st = ensure_ws(h, sizeof(double) * (2 * n_dinv + (size_t)trsm_workspace(n)));
@@ -807,7 +816,7 @@ gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const
     double* Dinv = (double*)h->ws;
     double* Cpl = Dinv + n_dinv;
     double* Y = Cpl + n_dinv;
-    GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+    GPC_HIP(h, diag_block_inverses(s, n, b, L, ldl, Dinv, Cpl));
     GPC_HIP(h, trsm_couplings(s, trans, n, L, ldl, Dinv, b, Cpl));
     GPC_HIP(h, trsm_blocked(s, trans, n, nrhs, L, ldl, Dinv, Cpl, b, B, ldb, Y));
     return GPC_OK;
@@ -837,7 +846,7 @@ gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, 
         return GPC_ERR_ARG;
     hipStream_t s = h->stream;
     if (n > 0) {
-        const int b = kDiagMax;   // solves sweep 128-blocks
+        const int b = solve_block(n);
         const int64_t nblk = (n + b - 1) / b;
         const size_t n_dinv = (size_t)nblk * b * b;
         gpc_status st = ensure_ws(h, sizeof(double) * (3 * n_dinv + (size_t)trsm_workspace(n)));
@@ -846,7 +855,7 @@ gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, 
         double* Cf = Dinv + n_dinv;
         double* Cb = Cf + n_dinv;
         double* Y = Cb + n_dinv;
-        GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+        GPC_HIP(h, diag_block_inverses(s, n, b, L, ldl, Dinv, Cf));
         GPC_HIP(h, trsm_couplings(s, 0, n, L, ldl, Dinv, b, Cf));
         GPC_HIP(h, trsm_couplings(s, 1, n, L, ldl, Dinv, b, Cb));
         GPC_HIP(h, vec_copy(s, n, y, z));
@@ -896,7 +905,7 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
         GPC_HIP(h, vec_zero(s, 1, eta));
         return GPC_OK;
     }
-    const int b = kDiagMax;   // solves sweep 128-blocks
+    const int b = solve_block(n);
     const int64_t nblk = (n + b - 1) / b;
     const size_t n_dinv = (size_t)nblk * b * b;
     const size_t n_part = (size_t)symv_parts(n);
@@ -910,7 +919,7 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
     double* rowabs = part + n_part;
     double* r = rowabs + n;
     double* d = r + n;
-    GPC_HIP(h, trtri_diag_batched(s, n, b, L, ldl, Dinv));
+    GPC_HIP(h, diag_block_inverses(s, n, b, L, ldl, Dinv, Cf));
     GPC_HIP(h, trsm_couplings(s, 0, n, L, ldl, Dinv, b, Cf));
     GPC_HIP(h, trsm_couplings(s, 1, n, L, ldl, Dinv, b, Cb));
     GPC_HIP(h, symv_lower(s, n, K, ldk, nullptr, 1, nullptr, 1.0, rowabs, part));

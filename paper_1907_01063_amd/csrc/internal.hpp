@@ -66,6 +66,11 @@ hipError_t trtri_diag_batched(hipStream_t s, int64_t n, int b, const double* L, 
 // leading dimension 256 (the rest of each 256-block is left untouched).
 hipError_t trtri_diag_pairs(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Dinv);
 hipError_t fill_f64(hipStream_t s, int64_t count, double* p, double v);
+// Inverses of the b x b diagonal blocks of L (b <= 128, or b = 256 composed
+// from the two 128 halves), lower with zero strict upper, at Dinv + q*b*b.
+// Tmp: ceil(n/b) * 128 * 128 doubles of scratch (b = 256 only).
+hipError_t diag_block_inverses(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl, double* Dinv,
+                               double* Tmp);
 
 // ---- elementwise helpers ---------------------------------------------------
 // Lf[i][j] = (float)L[i][j] for j < i (strict lower triangle only).
@@ -86,7 +91,7 @@ hipError_t reduce_tril(hipStream_t s, int b, const double* D, int64_t ldd, const
 hipError_t trsm_couplings(hipStream_t s, int trans, int64_t n, const double* L, int64_t ldl,
                           const double* Dinv, int b, double* C);
 // B <- L^-1 B (trans 0) or L^-T B (trans 1) by block steps with Dinv and the
-// couplings of the same direction (block b = kDiagMax).  Y: workspace of
+// couplings of the same direction (block b = 128 or 256).  Y: workspace of
 // trsm_workspace(n) doubles.
 int64_t trsm_workspace(int64_t n);
 hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L,

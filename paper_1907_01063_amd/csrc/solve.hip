@@ -22,85 +22,72 @@ namespace gpc {
 namespace {
 
 constexpr int kRhsGroup = 8;   // right-hand sides handled per launch
+constexpr int kSolveMax = 256; // largest block size of the sweeps
 constexpr int kRows = 64;      // rows per workgroup of the forward update
 
-// Partial dot product of one quarter of a 128-wide row with z (thread quarter
-// q covers columns q, q+4, ..., so the four threads of a row read adjacent
-// words); all loads are independent and issued before any arithmetic.
-__device__ __forceinline__ void quarter_dot(const double* row, int bq, int q, int nr,
-                                            const double (*z)[kRhsGroup], double* acc)
-{
-    double v[32];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        const int c = q + 4 * k;
-        v[k] = c < bq ? row[c] : 0.0;
-    }
-    for (int c = 0; c < nr; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            const int cc = q + 4 * k;
-            s += v[k] * (cc < bq ? z[cc][c] : 0.0);
-        }
-        acc[c] = s;
-    }
-}
-
-// Combine the four quarter sums of each row (adjacent lanes), fixed order.
-__device__ __forceinline__ double quad_sum(double v)
-{
-    const double a = __shfl_xor(v, 1, 64);      // partner in the pair
-    const double p = (threadIdx.x & 1) ? a + v : v + a;
-    const double b = __shfl_xor(p, 2, 64);
-    return (threadIdx.x & 2) ? b + p : p + b;
-}
-
-// rows [r0, r1): Y[r] -= L[r, j:j+bq] z   (z in LDS, bq <= 128); four threads per row
-__device__ void fwd_rows(int64_t r0, int64_t r1, int64_t j, int bq, int nr, const double* L, int64_t ldl,
+// rows [r0, r1): Y[r] -= L[r, j:j+BS] z (z in LDS).  TPR = BS/32 threads per
+// row, thread slot q covering columns q, q+TPR, ... (adjacent threads read
+// adjacent words); all loads issued before any arithmetic; the TPR partial
+// sums of a row are combined in a fixed order.
+template <int BS>
+__device__ void fwd_rows(int64_t r0, int64_t r1, int64_t j, int nr, const double* L, int64_t ldl,
                          const double (*z)[kRhsGroup], double* Y, int64_t ldy)
 {
-    const int q = threadIdx.x & 3;
-    for (int64_t rb = r0; rb < r1; rb += 64) {
-        const int64_t r = rb + (threadIdx.x >> 2);
+    constexpr int TPR = BS / 32, RPP = 256 / TPR;   // rows per pass
+    const int q = threadIdx.x % TPR;
+    for (int64_t rb = r0; rb < r1; rb += RPP) {
+        const int64_t r = rb + threadIdx.x / TPR;
         double acc[kRhsGroup];
-        if (r < r1) quarter_dot(L + r * ldl + j, bq, q, nr, z, acc);
-        else for (int c = 0; c < nr; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int c = 0; c < kRhsGroup; ++c) acc[c] = 0.0;
+        if (r < r1) {
+            const double* row = L + r * ldl + j;
+            double v[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) v[k] = row[q + TPR * k];
+            for (int c = 0; c < nr; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < 32; ++k) t += v[k] * z[q + TPR * k][c];
+                acc[c] = t;
+            }
+        }
         for (int c = 0; c < nr; ++c) {
-            const double t = quad_sum(acc[c]);
-            if (q == 0 && r < r1) Y[r * ldy + c] -= t;
+            double v = acc[c];
+#pragma unroll
+            for (int w = 1; w < TPR; w <<= 1) {
+                const double o = __shfl_xor(v, w, 64);
+                v = (threadIdx.x & w) ? o + v : v + o;
+            }
+            if (q == 0 && r < r1) Y[r * ldy + c] -= v;
         }
     }
 }
 
-// acc[c] = sum_t L[j+t][r] z[t][c] over t in [t0, t1) for one column r
-// (t1 - t0 <= 32); the loads are independent and issued together.
-__device__ __forceinline__ void bwd_col(int64_t r, int64_t j, int t0, int t1, int nr, const double* L, int64_t ldl,
-                                        const double (*z)[kRhsGroup], double* acc)
-{
-    double v[32];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) v[k] = t0 + k < t1 ? L[(j + t0 + k) * ldl + r] : 0.0;
-    for (int c = 0; c < nr; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 32; ++k) s += v[k] * (t0 + k < t1 ? z[t0 + k][c] : 0.0);
-        acc[c] = s;
-    }
-}
-
-// cols [r0, r0+64): Y[r] -= sum_t L[j+t][r] z[t], t split over the 4 waves and
-// combined in wave order.
+// cols [r0, r1) (at most 64): Y[r] -= sum_t L[j+t][r] z[t] over t < bq, t
+// split over the 4 waves (BS/4 each) and combined in wave order.
+template <int BS>
 __device__ void bwd_cols(int64_t r0, int64_t r1, int64_t j, int bq, int nr, const double* L, int64_t ldl,
                          const double (*z)[kRhsGroup], double* Y, int64_t ldy, double (*red)[64][kRhsGroup])
 {
+    constexpr int TW = BS / 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t r = r0 + lane;
-    const int q4 = (bq + 3) / 4;
-    const int t0 = min(bq, wave * q4), t1 = min(bq, t0 + q4);
+    const int t0 = wave * TW;
     double acc[kRhsGroup];
-    if (r < r1) bwd_col(r, j, t0, t1, nr, L, ldl, z, acc);
-    else for (int c = 0; c < nr; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < kRhsGroup; ++c) acc[c] = 0.0;
+    if (r < r1) {
+        double v[TW];
+#pragma unroll
+        for (int k = 0; k < TW; ++k) v[k] = t0 + k < bq ? L[(j + t0 + k) * ldl + r] : 0.0;
+        for (int c = 0; c < nr; ++c) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int k = 0; k < TW; ++k) sacc += v[k] * z[t0 + k][c];
+            acc[c] = sacc;
+        }
+    }
     for (int c = 0; c < nr; ++c) red[wave][lane][c] = acc[c];
     __syncthreads();
     if (wave == 0 && r < r1)
@@ -109,19 +96,18 @@ __device__ void bwd_cols(int64_t r0, int64_t r1, int64_t j, int bq, int nr, cons
     __syncthreads();
 }
 
-constexpr int kLook = 8;        // lookahead workgroups (16 rows of the next block each)
-
 // Forward lookahead: rows [i0, i0+16) of z_next = Dinv y_next - Cf z_cur for
-// the block [jn, jn + bn) (bn <= 128 rows; z_cur has bc entries, 0 if none).
-// 16 threads per row, thread k-slot s covers columns s, s+16, ...; the 16
+// the block [jn, jn + bn) (bn <= BS rows; z_cur has bc entries, 0 if none).
+// 16 threads per row, thread slot s covers columns s, s+16, ...; the 16
 // partial sums of a row are combined in a fixed order.
-__device__ void fwd_look(int i0, int bn, int bc, int nr, const double* Dn, const double* Cf, int b,
+template <int BS>
+__device__ void fwd_look(int i0, int bn, int bc, int nr, const double* Dn, const double* Cf,
                          const double* Y, int64_t jn, int64_t ldy, const double* zcur, double* znext, double* B,
                          int64_t ldb)
 {
-    __shared__ double ys[kDiagMax][kRhsGroup];
-    __shared__ double zs[kDiagMax][kRhsGroup];
-    for (int e = threadIdx.x; e < kDiagMax * kRhsGroup; e += 256) {
+    __shared__ double ys[BS][kRhsGroup];
+    __shared__ double zs[BS][kRhsGroup];
+    for (int e = threadIdx.x; e < BS * kRhsGroup; e += 256) {
         const int r = e / kRhsGroup, c = e % kRhsGroup;
         ys[r][c] = (r < bn && c < nr) ? Y[(jn + r) * ldy + c] : 0.0;
         zs[r][c] = (r < bc && c < nr) ? zcur[e] : 0.0;
@@ -133,18 +119,18 @@ __device__ void fwd_look(int i0, int bn, int bc, int nr, const double* Dn, const
 #pragma unroll
     for (int c = 0; c < kRhsGroup; ++c) acc[c] = 0.0;
     if (i < bn) {
-        double dv[kDiagMax / 16], cv[kDiagMax / 16];
+        double dv[BS / 16], cv[BS / 16];
 #pragma unroll
-        for (int m = 0; m < kDiagMax / 16; ++m) {
+        for (int m = 0; m < BS / 16; ++m) {
             const int k = sl + 16 * m;
-            dv[m] = k <= i ? Dn[(int64_t)i * b + k] : 0.0;            // Dinv is lower
-            cv[m] = (Cf && k < bc) ? Cf[(int64_t)i * b + k] : 0.0;
+            dv[m] = k <= i ? Dn[(int64_t)i * BS + k] : 0.0;            // Dinv is lower
+            cv[m] = (Cf && k < bc) ? Cf[(int64_t)i * BS + k] : 0.0;
         }
 #pragma unroll
         for (int c = 0; c < kRhsGroup; ++c) {
             double t = 0.0;
 #pragma unroll
-            for (int m = 0; m < kDiagMax / 16; ++m) t += dv[m] * ys[sl + 16 * m][c] - cv[m] * zs[sl + 16 * m][c];
+            for (int m = 0; m < BS / 16; ++m) t += dv[m] * ys[sl + 16 * m][c] - cv[m] * zs[sl + 16 * m][c];
             acc[c] = t;
         }
     }
@@ -166,17 +152,18 @@ __device__ void fwd_look(int i0, int bn, int bc, int nr, const double* Dn, const
 }
 
 // Backward lookahead: rows [i0, i0+16) of x_prev = Dinv^T y_prev - Cb^T x_cur
-// for the full block [jp, jp + b) (x_cur has bc entries, 0 if none).  Thread
+// for the block [jp, jp + bp) (x_cur has bc entries, 0 if none).  Thread
 // (t-slot g, row i0 + l) covers t = g, g+16, ...; partial sums over the 16
 // t-slots are combined in a fixed order through LDS.
-__device__ void bwd_look(int i0, int bp, int bc, int nr, const double* Dp, const double* Cb, int b,
+template <int BS>
+__device__ void bwd_look(int i0, int bp, int bc, int nr, const double* Dp, const double* Cb,
                          const double* Y, int64_t jp, int64_t ldy, const double* xcur, double* xnext, double* B,
                          int64_t ldb)
 {
-    __shared__ double ys[kDiagMax][kRhsGroup];
-    __shared__ double xs[kDiagMax][kRhsGroup];
+    __shared__ double ys[BS][kRhsGroup];
+    __shared__ double xs[BS][kRhsGroup];
     __shared__ double red[16][16][kRhsGroup];
-    for (int e = threadIdx.x; e < kDiagMax * kRhsGroup; e += 256) {
+    for (int e = threadIdx.x; e < BS * kRhsGroup; e += 256) {
         const int r = e / kRhsGroup, c = e % kRhsGroup;
         ys[r][c] = (r < bp && c < nr) ? Y[(jp + r) * ldy + c] : 0.0;
         xs[r][c] = (r < bc && c < nr) ? xcur[e] : 0.0;
@@ -188,18 +175,18 @@ __device__ void bwd_look(int i0, int bp, int bc, int nr, const double* Dp, const
 #pragma unroll
     for (int c = 0; c < kRhsGroup; ++c) acc[c] = 0.0;
     if (i < bp) {
-        double dv[kDiagMax / 16], cv[kDiagMax / 16];
+        double dv[BS / 16], cv[BS / 16];
 #pragma unroll
-        for (int m = 0; m < kDiagMax / 16; ++m) {
+        for (int m = 0; m < BS / 16; ++m) {
             const int t = g + 16 * m;
-            dv[m] = (t >= i && t < bp) ? Dp[(int64_t)t * b + i] : 0.0;   // (Dinv^T)[i][t], Dinv lower
-            cv[m] = (Cb && t < bc) ? Cb[(int64_t)t * b + i] : 0.0;
+            dv[m] = (t >= i && t < bp) ? Dp[(int64_t)t * BS + i] : 0.0;   // (Dinv^T)[i][t], Dinv lower
+            cv[m] = (Cb && t < bc) ? Cb[(int64_t)t * BS + i] : 0.0;
         }
 #pragma unroll
         for (int c = 0; c < kRhsGroup; ++c) {
             double t2 = 0.0;
 #pragma unroll
-            for (int m = 0; m < kDiagMax / 16; ++m) t2 += dv[m] * ys[g + 16 * m][c] - cv[m] * xs[g + 16 * m][c];
+            for (int m = 0; m < BS / 16; ++m) t2 += dv[m] * ys[g + 16 * m][c] - cv[m] * xs[g + 16 * m][c];
             acc[c] = t2;
         }
     }
@@ -217,46 +204,50 @@ __device__ void bwd_look(int i0, int bp, int bc, int nr, const double* Dp, const
     }
 }
 
-// Forward sweep, launch q (q = -1: z_0 only).  Workgroups < kLook form the
+// Forward sweep, launch q (q = -1: z_0 only).  Workgroups < BS/16 form the
 // next block's z; the rest update the rows below the next block with z_q.
+template <int BS>
 __global__ void __launch_bounds__(256)
-trsv_fwd(int64_t n, int nr, int64_t q, int b, const double* L, int64_t ldl, const double* Dinv, const double* Cf,
+trsv_fwd(int64_t n, int nr, int64_t q, const double* L, int64_t ldl, const double* Dinv, const double* Cf,
          double* Y, int64_t ldy, const double* zcur, double* znext, double* B, int64_t ldb)
 {
-    const int64_t jn = (q + 1) * b;                       // next block
-    const int bn = (int)min((int64_t)b, n - jn);
-    const int bc = q >= 0 ? b : 0;                        // block q is full whenever a next block exists
+    constexpr int kLook = BS / 16;
+    const int64_t jn = (q + 1) * BS;                      // next block
+    const int bn = (int)min((int64_t)BS, n - jn);
+    const int bc = q >= 0 ? BS : 0;                       // block q is full whenever a next block exists
     if (blockIdx.x < kLook) {
-        fwd_look(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * b * b, q >= 0 ? Cf + (q + 1) * b * b : nullptr, b,
-                 Y, jn, ldy, zcur, znext, B, ldb);
+        fwd_look<BS>(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * BS * BS,
+                     q >= 0 ? Cf + (q + 1) * BS * BS : nullptr, Y, jn, ldy, zcur, znext, B, ldb);
     } else {
-        __shared__ double z[kDiagMax][kRhsGroup];
-        for (int e = threadIdx.x; e < kDiagMax * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
+        __shared__ double z[BS][kRhsGroup];
+        for (int e = threadIdx.x; e < BS * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
         __syncthreads();
         const int64_t r0 = jn + bn + (int64_t)(blockIdx.x - kLook) * kRows;
-        fwd_rows(r0, min(n, r0 + kRows), q * b, b, nr, L, ldl, z, Y, ldy);
+        fwd_rows<BS>(r0, min(n, r0 + kRows), q * BS, nr, L, ldl, z, Y, ldy);
     }
 }
 
-// Backward sweep, launch q (q = nblk: x_{nblk-1} only): workgroups < kLook
+// Backward sweep, launch q (q = nblk: x_{nblk-1} only): workgroups < BS/16
 // form x_{q-1}; the rest update the columns left of block q-1 with x_q.
+template <int BS>
 __global__ void __launch_bounds__(256)
-trsv_bwd(int64_t n, int nr, int64_t q, int64_t nblk, int b, const double* L, int64_t ldl, const double* Dinv,
+trsv_bwd(int64_t n, int nr, int64_t q, int64_t nblk, const double* L, int64_t ldl, const double* Dinv,
          const double* Cb, double* Y, int64_t ldy, const double* xcur, double* xnext, double* B, int64_t ldb)
 {
-    const int64_t jp = (q - 1) * b;                       // previous block
-    const int bp = (int)min((int64_t)b, n - jp);
-    const int bc = q < nblk ? (int)min((int64_t)b, n - q * b) : 0;
+    constexpr int kLook = BS / 16;
+    const int64_t jp = (q - 1) * BS;                      // previous block
+    const int bp = (int)min((int64_t)BS, n - jp);
+    const int bc = q < nblk ? (int)min((int64_t)BS, n - q * BS) : 0;
     if (blockIdx.x < kLook) {
-        bwd_look(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * b * b, q < nblk ? Cb + (q - 1) * b * b : nullptr, b,
-                 Y, jp, ldy, xcur, xnext, B, ldb);
+        bwd_look<BS>(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * BS * BS,
+                     q < nblk ? Cb + (q - 1) * BS * BS : nullptr, Y, jp, ldy, xcur, xnext, B, ldb);
     } else {
-        __shared__ double z[kDiagMax][kRhsGroup];
+        __shared__ double z[BS][kRhsGroup];
         __shared__ double red[4][64][kRhsGroup];
-        for (int e = threadIdx.x; e < kDiagMax * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = xcur[e];
+        for (int e = threadIdx.x; e < BS * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = xcur[e];
         __syncthreads();
         const int64_t r0 = (int64_t)(blockIdx.x - kLook) * 64;
-        if (r0 < jp) bwd_cols(r0, min(jp, r0 + 64), q * b, bc, nr, L, ldl, z, Y, ldy, red);
+        if (r0 < jp) bwd_cols<BS>(r0, min(jp, r0 + 64), q * BS, bc, nr, L, ldl, z, Y, ldy, red);
     }
 }
 
@@ -284,7 +275,7 @@ __global__ void __launch_bounds__(256) logdet_kernel(int64_t n, const double* L,
 
 }  // namespace
 
-int64_t trsm_workspace(int64_t n) { return (int64_t)kRhsGroup * n + 2 * kDiagMax * kRhsGroup; }
+int64_t trsm_workspace(int64_t n) { return (int64_t)kRhsGroup * n + 2 * kSolveMax * kRhsGroup; }
 
 hipError_t trsm_couplings(hipStream_t s, int trans, int64_t n, const double* L, int64_t ldl, const double* Dinv,
                           int b, double* C)
@@ -347,13 +338,15 @@ hipError_t trsm_couplings(hipStream_t s, int trans, int64_t n, const double* L, 
     return hipSuccess;
 }
 
-hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
-                        const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb, double* Y)
+namespace {
+template <int BS>
+hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
+                 const double* Dinv, const double* Cpl, double* B, int64_t ldb, double* Y)
 {
-    if (b != kDiagMax) return hipErrorInvalidValue;
-    const int64_t nblk = (n + b - 1) / b;
+    constexpr int kLook = BS / 16;
+    const int64_t nblk = (n + BS - 1) / BS;
     double* zb = Y + (int64_t)kRhsGroup * n;            // two z slots
-    auto zslot = [&](int64_t q) { return zb + (q & 1) * kDiagMax * kRhsGroup; };
+    auto zslot = [&](int64_t q) { return zb + (q & 1) * kSolveMax * kRhsGroup; };
     for (int64_t c0 = 0; c0 < nrhs; c0 += kRhsGroup) {
         const int nr = (int)std::min<int64_t>(kRhsGroup, nrhs - c0);
         double* Bc = B + c0;
@@ -361,24 +354,33 @@ hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const
                            (int64_t)kRhsGroup);
         if (!trans) {
             for (int64_t q = -1; q + 1 < nblk; ++q) {
-                const int64_t jn = (q + 1) * b;
-                const int64_t rest = n - std::min(n, jn + b);
+                const int64_t jn = (q + 1) * BS;
+                const int64_t rest = n - std::min(n, jn + BS);
                 const int64_t blocks = kLook + (q >= 0 ? (rest + kRows - 1) / kRows : 0);
-                hipLaunchKernelGGL(trsv_fwd, dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, b, L, ldl, Dinv, Cpl,
-                                   Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
+                hipLaunchKernelGGL((trsv_fwd<BS>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, L, ldl, Dinv,
+                                   Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
             }
         } else {
             for (int64_t q = nblk; q >= 1; --q) {
-                const int64_t jp = (q - 1) * b;
+                const int64_t jp = (q - 1) * BS;
                 const int64_t blocks = kLook + (q < nblk ? (jp + 63) / 64 : 0);
-                hipLaunchKernelGGL(trsv_bwd, dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, nblk, b, L, ldl, Dinv,
-                                   Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
+                hipLaunchKernelGGL((trsv_bwd<BS>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, nblk, L, ldl,
+                                   Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
             }
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+}  // namespace
+
+hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
+                        const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb, double* Y)
+{
+    if (b == 128) return sweep<128>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y);
+    if (b == 256) return sweep<256>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y);
+    return hipErrorInvalidValue;
 }
 
 hipError_t logdet(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* out)
