@@ -1,15 +1,16 @@
-// Diagonal-block kernels: one workgroup owns one kb x kb block (kb <= 128)
-// held entirely in LDS (128 x 129 doubles = 132 KB of the CU's 160 KB).
+// Diagonal-block kernels, one workgroup per block (kb <= 128).
 //
-// potrf_diag: the classic unblocked Cholesky of the diagonal block, the
-// "chol" step of section 3.3.1, and in the same sweep the inverse of the
-// resulting triangle (needed by the panel solve L21 = A21 L11^-T, done as a
-// product with the inverse as the paper does with its lower-triangular
-// inverse, section 3.2).  Held in registers, see potrf_diag_kernel.
+// potrf_diag: Cholesky of the diagonal block, the "chol" step of section
+// 3.3.1, and in the same sweep the inverse of the resulting triangle (needed
+// by the panel solve L21 = A21 L11^-T, done as a product with the inverse as
+// the paper does with its lower-triangular inverse, section 3.2): 16 x 16
+// tiles held in registers and updated with matrix-core products, see
+// diag_tile_factor_inverse.
 //
 // trtri_diag_batched: inverses of all diagonal blocks of a given factor, one
-// workgroup per block (the D^-1 of each step of the reverse sweep, 3.3.2);
-// block q goes to Dinv + q*b*b with leading dimension b.
+// workgroup per block held in LDS (128 x 129 doubles = 132 KB of the CU's
+// 160 KB): the D^-1 of each step of the reverse sweep (3.3.2); block q goes
+// to Dinv + q*b*b with leading dimension b.
 #include "diag.hpp"
 
 namespace gpc {
@@ -60,14 +61,15 @@ __device__ void invert_in_lds(double* S, double* xd, int kb)
     __syncthreads();
 }
 
-// NA: 16-row groups held per thread (blocks up to 16 NA; smaller blocks take
-// the smaller instance, whose per-column work is proportionally smaller).
-template <int NA>
-__global__ void __launch_bounds__(256)
-potrf_diag_kernel(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info, int64_t col0)
+// NT: 16 x 16 tile rows of the block (blocks up to 16 NT; smaller blocks take
+// the smaller instance).  At most 256 registers per lane, so that the kernel
+// fits on a CU beside a product kernel's workgroup.
+template <int NT>
+__global__ void __launch_bounds__(256, 2)
+potrf_tile_kernel(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info, int64_t col0)
 {
-    __shared__ double colbuf[2 * 16 * NA], rowbuf[2 * 16 * NA], piv[4], rls[16 * NA];
-    diag_factor_inverse<NA>(kb, A, lda, Linv, ldi, info, col0, colbuf, rowbuf, piv, rls);
+    __shared__ double F[NT * 256], LU[256];
+    diag_tile_factor_inverse<NT>(kb, A, lda, Linv, ldi, info, col0, F, LU);
 }
 
 __global__ void __launch_bounds__(256)
@@ -145,11 +147,11 @@ hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Lin
     if (kb <= 0) return hipSuccess;
     if (kb > kDiagMax || lda > (int64_t(1) << 20)) return hipErrorInvalidValue;   // 31-bit row-band offsets
     if (kb <= 32)
-        hipLaunchKernelGGL(potrf_diag_kernel<2>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
+        hipLaunchKernelGGL(potrf_tile_kernel<2>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
     else if (kb <= 64)
-        hipLaunchKernelGGL(potrf_diag_kernel<4>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
+        hipLaunchKernelGGL(potrf_tile_kernel<4>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
     else
-        hipLaunchKernelGGL(potrf_diag_kernel<kDiagMax / 16>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info,
+        hipLaunchKernelGGL(potrf_tile_kernel<kDiagMax / 16>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info,
                            col0);
     return hipGetLastError();
 }

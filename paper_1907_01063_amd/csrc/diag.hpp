@@ -32,148 +32,330 @@ __device__ __forceinline__ double rsqrt_refined(double d)
     return y;
 }
 
-// Factor + inverse of one diagonal block with the block held in registers.
-// Thread (ty, tx) of a 16 x 16 grid owns the elements (i, c) = (ty + 16a, tx + 16b)
-// with a >= b (the lower triangle, up to 36 per thread) in E[a][b] for the
-// whole kernel.  Column j takes one barrier:
-//   publish  the owners of column j put the unscaled E(i, j) in colbuf (zero
-//            for i <= j and i >= kb) and restart those registers as the
-//            inverse's column j; the owners of row j put the inverse's
-//            unscaled row X_jc (c < j), 1 at c = j and zeros beyond in rowbuf;
-//            the owner of (j, j) takes d = E(j,j), records a failed pivot,
-//            writes L_jj = sqrt(d) and publishes 1/d and 1/L_jj;        barrier
-//   update   the owners of column j write L_ij = E(i,j) / L_jj; every thread
-//            updates its elements in rows i > j with one multiply-add,
-//            f_c = (c > j ? colbuf_c : rowbuf_c) / d:
-//              c > j:  E -= E(i,j) E(c,j) / d = L_ij L_cj   (Schur complement)
-//              c <= j: E -= E(i,j) X_jc / d = L_ij Xh_jc    (inverse by forward
-//                      substitution, Xh_jc = X_jc / L_jj)
-// so the factor of section 3.3.1's diagonal step and its inverse (used by the
-// panel solve) come out of the same sweep.  E(i, c), c < i, ends as the
-// inverse's unscaled entry X_ic; the inverse is written once at the end as
-// Xh_ic = X_ic / L_ii.  The broadcast buffers alternate between columns: a
-// thread that publishes column j + 2 has passed the barrier of column j + 1,
-// which every thread reaches only after its update with column j.  LDS use
-// is small (about 5 KB at NA = 8), so the kernel can share a CU with the
-// product kernels that run beside it.
-// NA: number of 16-row groups (block edge up to 16 * NA); 256 threads.
-// colbuf, rowbuf: 2 * 16 * NA doubles; piv: 4 doubles; rls: 16 * NA doubles
-// (all LDS).  A and Linv: byte offsets of a 16 NA row band fit in 31 bits.
-template <int NA>
-__device__ void diag_factor_inverse(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info,
-                                    int64_t col0, double* colbuf, double* rowbuf, double* piv, double* rls)
+// ---- tiled factor + inverse with matrix-core products ----------------------
+// FP64 MFMA 16x16x4 layouts: the A operand of k-slice kk holds A[l%16][l/16 +
+// 4kk] in lane l, the B operand B[l/16 + 4kk][l%16], and the 4 accumulator
+// registers hold rows l/16 + 4r of column l%16 ("C layout").  So a tile kept
+// in C layout is, register kk for register kk, the B operand of itself; and a
+// tile's C-layout registers stored to LDS as [r][lane] read back at
+// [kk][lane] as the A operand of that tile's transpose.
+typedef double dtile __attribute__((ext_vector_type(4)));
+
+// value selects (a conditional over two lvalues would select their addresses)
+template <typename V>
+__device__ __forceinline__ V pick(bool c, V a, V b)
 {
-    constexpr int NB = 16 * NA;
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-    const __amdgpu_buffer_rsrc_t ra =
-        __builtin_amdgcn_make_buffer_rsrc(A, (short)0, 0x7fffffff, 0x00020000);
+    return c ? a : b;
+}
 
-    double E[NA][NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = ty + 16 * a, c = tx + 16 * b;
-            E[a][b] = (i < kb && c <= i) ? A[i * lda + c] : 0.0;
-        }
-    // wait for the block's loads here, once: otherwise the wait for them sits
-    // inside the column loop, where it also waits for every store of L issued
-    // by the previous columns
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-    // byte offset of row ty + 16a of A
-    uint32_t rowoff[NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) rowoff[a] = (uint32_t)((ty + 16 * a) * lda) * 8u;
+// orders LDS accesses between the lanes of one wave
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-#pragma unroll
-    for (int aj = 0; aj < NA; ++aj) {
-        if (aj * 16 >= kb) break;
-        for (int rj = 0; rj < 16; ++rj) {
-            const int j = aj * 16 + rj;
-            if (j >= kb) break;
-            double* cb = colbuf + (j & 1) * NB;
-            double* rb = rowbuf + (j & 1) * NB;
-            double* pv = piv + (j & 1) * 2;
-            // publish
-            if (tx == rj) {
-#pragma unroll
-                for (int a = aj; a < NA; ++a) {
-                    const int i = ty + 16 * a;
-                    const bool below = i > j && i < kb;
-                    cb[i] = below ? E[a][aj] : 0.0;
-                    if (below) E[a][aj] = 0.0;
-                }
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// every lane takes v from lane J of its own row of 16 lanes
+template <int J>
+__device__ __forceinline__ double row_bcast_f64(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x150 + J, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x150 + J, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// the transpose of a C-layout tile, stored to LDS so that [kk][lane] reads
+// give the A operand of the tile itself (T[l%16][l/16 + 4kk])
+__device__ __forceinline__ void store_tile_transposed(double* buf, const dtile& t, int lane)
+{
+    double* q = buf + ((lane & 15) >> 2) * 64 + 16 * (lane & 3) + (lane >> 4);
+    static_for<0, 4>([&](auto R_) {
+        constexpr int r = decltype(R_)::value;
+        q[4 * r] = t[r];
+    });
+}
+
+__device__ __forceinline__ void store_tile(double* buf, const dtile& t, int lane)
+{
+    static_for<0, 4>([&](auto R_) {
+        constexpr int r = decltype(R_)::value;
+        buf[r * 64 + lane] = t[r];
+    });
+}
+
+// acc + A B, with the A fragments in af and the B fragments in bf
+__device__ __forceinline__ dtile mfma_tile(const double (&af)[4], const dtile& bf, dtile acc)
+{
+    static_for<0, 4>([&](auto KK_) {
+        constexpr int kk = decltype(KK_)::value;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk], bf[kk], acc, 0, 0, 0);
+    });
+    return acc;
+}
+
+__device__ __forceinline__ void load_frags(const double* buf, int lane, double (&f)[4], double sign)
+{
+    static_for<0, 4>([&](auto KK_) {
+        constexpr int kk = decltype(KK_)::value;
+        f[kk] = sign * buf[kk * 64 + lane];
+    });
+}
+
+__device__ __forceinline__ dtile load_bfrag(const double* buf, int lane)
+{
+    dtile t;
+    static_for<0, 4>([&](auto KK_) {
+        constexpr int kk = decltype(KK_)::value;
+        t[kk] = buf[kk * 64 + lane];
+    });
+    return t;
+}
+
+// One wave factors the symmetric 16 x 16 tile E (C layout, both triangles)
+// and inverts the factor: a column sweep entirely in registers, with the
+// column's entries taken from the lanes that hold them (no LDS, no barrier).
+// Step j: d = E(j, j); every row rho > j takes E(rho, c) -= E(rho, j) f_c
+// with f_c = E(j, c) / d (c != j; E(j, c) is the Schur complement's entry
+// for c > j and the running inverse's unscaled row j for c < j) and restarts
+// column j as the inverse's column, E(rho, j) = -E(rho, j) / d.  The lanes of
+// column j keep its unscaled entries and 1/sqrt(d); the factor's tile is
+// formed from them at the end.  On return E holds the inverse Linv (C layout,
+// zero above the diagonal), lt the factor's tile (zero above the diagonal);
+// the first failed pivot is recorded in info.
+__device__ __forceinline__ void factor_tile16(dtile& E, dtile& lt, int lane, int32_t* info, int64_t col0)
+{
+    // the lane's column and row group, recomputed here so that the per-step
+    // lane masks are formed where they are used rather than kept live
+    int c, g;
+    asm volatile("v_and_b32 %0, 15, %1" : "=v"(c) : "v"(lane));
+    asm volatile("v_lshrrev_b32 %0, 4, %1" : "=v"(g) : "v"(lane));
+    dtile yr = {0.0, 0.0, 0.0, 0.0};                       // 1/L_rr of the lane's rows
+    lt = dtile{0.0, 0.0, 0.0, 0.0};                        // unscaled column c of L
+    double ycol = 0.0;                                     // 1/L_cc
+    int fail = 0;
+    static_for<0, 16>([&](auto J) {
+        constexpr int j = decltype(J)::value, jr = j / 4, jg = j % 4;
+        const double d = readlane_f64(E[jr], 16 * jg + j);
+        const double ejc = __shfl(E[jr], 16 * jg + c, 64);
+        double eij[4];
+        static_for<jr, 4>([&](auto R_) {
+            constexpr int r = decltype(R_)::value;
+            eij[r] = row_bcast_f64<j>(E[r]);
+        });
+        fail = (fail == 0 && !(d > 0.0)) ? j + 1 : fail;
+        const double y = rsqrt_refined(d);
+        const double rd = y * y;
+        const bool own = c == j;
+        const double f = pick<double>(own, rd, ejc * rd);
+        ycol = pick<double>(own, y, ycol);
+        static_for<jr, 4>([&](auto R_) {
+            constexpr int r = decltype(R_)::value;
+            lt[r] = pick<double>(own, E[r], lt[r]);
+            const double upd = pick<double>(own, 0.0, E[r]) - eij[r] * f;
+            if constexpr (r == jr) {
+                E[r] = pick<double>(g > jg, upd, E[r]);
+                yr[r] = pick<double>(g == jg, y, yr[r]);
+            } else {
+                E[r] = upd;
             }
-            if (ty == rj) {
-#pragma unroll
-                for (int b = 0; b < NA; ++b) {
-                    const int c = tx + 16 * b;
-                    rb[c] = b <= aj ? (c < j ? E[aj][b] : (c == j ? 1.0 : 0.0)) : 0.0;
-                }
-                if (tx == rj) {
-                    const double d = E[aj][aj];
-                    if (!(d > 0.0) && *info == 0) *info = (int32_t)(col0 + j + 1);
-                    const double y = rsqrt_refined(d);
-                    double l = d * y;                      // sqrt(d), one correction step
-                    l = fma(0.5 * y, fma(-l, l, d), l);
-                    pv[0] = y * y;
-                    pv[1] = y;
-                    rls[j] = y;
-                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, l),
-                                                          ra, (int)(rowoff[aj] + 8u * j), 0, 0);
-                }
+        });
+    });
+    if (fail != 0 && lane == 0 && *info == 0) *info = (int32_t)(col0 + fail);
+    static_for<0, 4>([&](auto R_) {
+        constexpr int r = decltype(R_)::value;
+        const int rho = g + 4 * r;
+        E[r] = c < rho ? E[r] * yr[r] : (c == rho ? yr[r] : 0.0);
+        const double dd = lt[r];
+        double l = dd * ycol;                              // sqrt(d), one correction step
+        l = fma(0.5 * ycol, fma(-l, l, dd), l);
+        lt[r] = c < rho ? dd * ycol : (c == rho ? l : 0.0);
+    });
+}
+
+// Factor + inverse of one kb x kb diagonal block (kb <= 16 NT) by tiles, the
+// "chol" step of section 3.3.1 together with the inverse the panel solve
+// multiplies by (section 3.2).  The block is NT x NT tiles of 16 x 16, the
+// lower ones (i >= c) held in registers in C layout for the whole kernel:
+// wave w < NT/2 owns tile rows w and NT-1-w (NT + 1 tiles: tile (w, c) in
+// T[c], tile (NT-1-w, c) in T[NT-c]).  For each tile column p:
+//   A  the owner of row p updates tile (p, p) with column p-1 (step C of
+//      p-1, taken first), factors and inverts it (one wave), writes L_pp and
+//      puts Linv_pp's transpose in LDS; the other owners finish step C of
+//      column p-1;                                                 barrier
+//   B  owners of rows i > p: L_ip^T = Linv_pp S_ip^T (S_ip = tile (i, p)),
+//      written to A and to the panel buffer F[i]; the owner of row p turns
+//      its running inverse tiles R_pc (c < p) into the final inverse tiles
+//      X_pc = Linv_pp R_pc, and puts them and X_pp = Linv_pp in F[c];  barrier
+//   C  owners of rows i > p update every tile (i, c), c <= i:
+//        c > p:  S_ic -= L_ip L_cp^T      (Schur complement)
+//        c = p:  R_ip  = -L_ip Linv_pp    (restarts as a running inverse tile)
+//        c < p:  R_ic -= L_ip X_pc        (forward substitution)
+// Rows and columns past kb act as an identity block.  The inverse tiles are
+// written at the end, with the strict upper triangles of both outputs zeroed.
+// F: NT * 256 doubles, LU: 256 doubles (LDS).  256 threads.
+template <int NT>
+__device__ void diag_tile_factor_inverse(int kb, double* A, int64_t lda, double* Linv, int64_t ldi,
+                                         int32_t* info, int64_t col0, double* F, double* LU)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool active = w < NT / 2;
+    const int rowA = w, rowB = NT - 1 - w;             // owned tile rows
+    const int np = (kb + 15) >> 4;                     // tile rows holding part of the block
+    const int lr = lane >> 4, lc = lane & 15;          // C layout: rows lr + 4r, column lc
+    const dtile zero = {0.0, 0.0, 0.0, 0.0};
+
+    dtile T[NT + 1];
+    static_for<0, NT + 1>([&](auto I) { T[decltype(I)::value] = zero; });
+    // tile (i, c) element (16i + lr + 4r, 16c + lc); the diagonal tiles in
+    // full from the lower triangle; identity past kb
+    static_for<0, 2>([&](auto RI) {
+        constexpr int ri = decltype(RI)::value;
+        const int i = ri == 0 ? rowA : rowB;
+        static_for<0, NT>([&](auto CC) {
+            constexpr int cc = decltype(CC)::value;
+            constexpr int idx = ri == 0 ? cc : NT - cc;
+            if (active && cc <= i && i < np) {
+                static_for<0, 4>([&](auto R_) {
+                    constexpr int r = decltype(R_)::value;
+                    const int a = 16 * i + lr + 4 * r, b = 16 * cc + lc;
+                    const int hi = a > b ? a : b, lo = a > b ? b : a;
+                    T[idx][r] = hi < kb ? A[(int64_t)hi * lda + lo] : (a == b ? 1.0 : 0.0);
+                });
             }
-            __syncthreads();
-            // update (rows i > j only: a >= aj)
-            const double rd = pv[0], rl = pv[1];
-            double g[NA], f[NA];
-#pragma unroll
-            for (int a = aj; a < NA; ++a) g[a] = cb[ty + 16 * a];
-            if (tx == rj) {
-#pragma unroll
-                for (int a = aj; a < NA; ++a) {
-                    const int i = ty + 16 * a;
-                    if (i > j && i < kb)
-                        __builtin_amdgcn_raw_buffer_store_b64(
-                            __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, g[a] * rl), ra,
-                            (int)(rowoff[a] + 8u * j), 0, 0);
-                }
+        });
+    });
+
+    for (int p = 0; p < np; ++p) {
+        // ---- A: the owner of row p (tile (p, p) is T[p] or T[NT-p])
+        const bool pA = active && w == p, pB = active && w == NT - 1 - p;
+        if (pA || pB) {
+            const int di = pA ? p : NT - p;
+            dtile D = zero;
+            static_for<0, NT + 1>([&](auto I) {           // selects, not branches, keep T in registers
+                const dtile v = T[decltype(I)::value];
+                D = pick<dtile>(decltype(I)::value == di, v, D);
+            });
+            if (p > 0) {
+                double ai[4];
+                load_frags(F + p * 256, lane, ai, -1.0);
+                D = mfma_tile(ai, load_bfrag(F + p * 256, lane), D);
             }
-#pragma unroll
-            for (int b = 0; b < NA; ++b) {
-                // colbuf is fresh only in rows >= 16 aj; columns c < 16 aj are <= j
-                const int c = tx + 16 * b;
-                f[b] = (b < aj ? rb[c] : (b > aj ? cb[c] : (c > j ? cb[c] : rb[c]))) * rd;
-            }
-#pragma unroll
-            for (int a = aj; a < NA; ++a)
-#pragma unroll
-                for (int b = 0; b <= a; ++b)
-                    E[a][b] -= g[a] * f[b];
+            dtile lt;
+            factor_tile16(D, lt, lane, info, col0 + 16 * p);
+            static_for<0, 4>([&](auto R_) {
+                constexpr int r = decltype(R_)::value;
+                const int a = 16 * p + lr + 4 * r, b = 16 * p + lc;
+                if (a < kb && b < kb) A[(int64_t)a * lda + b] = lt[r];
+            });
+            store_tile_transposed(LU, D, lane);
+            static_for<0, NT + 1>([&](auto I) {
+                const dtile v = T[decltype(I)::value];
+                T[decltype(I)::value] = pick<dtile>(decltype(I)::value == di, D, v);
+            });
         }
+        // ---- the rest of C for column p-1 (one B fragment load serves both rows)
+        if (active && p > 0) {
+            const int q = p - 1;
+            const bool okA = rowA > q && rowA < np, okB = rowB > q && rowB < np;
+            double aA[4], aB[4];                                 // -L_iq of the two rows
+            load_frags(F + rowA * 256, lane, aA, -1.0);
+            load_frags(F + rowB * 256, lane, aB, -1.0);
+            static_for<0, NT>([&](auto CC) {
+                constexpr int cc = decltype(CC)::value;
+                const bool useA = okA && cc <= rowA && !(cc == p && rowA == p);
+                const bool useB = okB && cc <= rowB && !(cc == p && rowB == p);
+                if (useA || useB) {
+                    const dtile b = load_bfrag(F + cc * 256, lane);
+                    if (useA) T[cc] = mfma_tile(aA, b, cc == q ? zero : T[cc]);
+                    if (useB) T[NT - cc] = mfma_tile(aB, b, cc == q ? zero : T[NT - cc]);
+                }
+            });
+        }
+        __syncthreads();
+        // ---- B
+        if (active) {
+            double la[4];
+            load_frags(LU, lane, la, 1.0);
+            static_for<0, 2>([&](auto RI) {
+                constexpr int ri = decltype(RI)::value;
+                const int i = ri == 0 ? rowA : rowB;
+                if (i > p && i < np) {
+                    double* Fi = F + i * 256;
+                    dtile sip = zero;                              // tile (i, p)
+                    static_for<0, NT>([&](auto CC) {
+                        constexpr int cc = decltype(CC)::value;
+                        const dtile v = T[ri == 0 ? cc : NT - cc];
+                        sip = pick<dtile>(cc == p, v, sip);
+                    });
+                    store_tile_transposed(Fi, sip, lane);
+                    wave_lds_sync();
+                    const dtile sb = load_bfrag(Fi, lane);
+                    const dtile lt = mfma_tile(la, sb, zero);                   // L_ip^T
+                    wave_lds_sync();
+                    store_tile(Fi, lt, lane);
+                    static_for<0, 4>([&](auto R_) {
+                        constexpr int r = decltype(R_)::value;
+                        const int a = 16 * i + lc, b = 16 * p + lr + 4 * r;
+                        if (a < kb) A[(int64_t)a * lda + b] = lt[r];
+                    });
+                }
+            });
+            static_for<0, 2>([&](auto RI) {
+                constexpr int ri = decltype(RI)::value;
+                if ((ri == 0 ? rowA : rowB) == p) {
+                    static_for<0, NT>([&](auto CC) {
+                        constexpr int cc = decltype(CC)::value;
+                        constexpr int idx = ri == 0 ? cc : NT - cc;
+                        if (cc < p) T[idx] = mfma_tile(la, T[idx], zero);
+                        if (cc <= p) store_tile(F + cc * 256, T[idx], lane);
+                    });
+                }
+            });
+        }
+        __syncthreads();
     }
-    __syncthreads();
+    // the last column's step C has no rows below it
 
-    // write out the inverse (row i scaled by 1/L_ii) and zero both upper halves
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = ty + 16 * a, c = tx + 16 * b;
-            if (i < kb && c <= i) Linv[i * ldi + c] = c < i ? E[a][b] * rls[i] : rls[i];
-        }
-    for (int idx = tid; idx < kb * kb; idx += 256) {
-        const int r = idx / kb, c = idx % kb;
-        if (c > r) {
-            A[r * lda + c] = 0.0;
-            Linv[r * ldi + c] = 0.0;
-        }
+    // write the inverse; zero the strict upper triangles of both outputs
+    if (active) {
+        static_for<0, 2>([&](auto RI) {
+            constexpr int ri = decltype(RI)::value;
+            const int i = ri == 0 ? rowA : rowB;
+            static_for<0, NT>([&](auto CC) {
+                constexpr int cc = decltype(CC)::value;
+                constexpr int idx = ri == 0 ? cc : NT - cc;
+                if (cc <= i && i < np) {
+                    static_for<0, 4>([&](auto R_) {
+                        constexpr int r = decltype(R_)::value;
+                        const int a = 16 * i + lr + 4 * r, b = 16 * cc + lc;
+                        if (a < kb && b < kb) Linv[(int64_t)a * ldi + b] = T[idx][r];
+                        if (cc < i) {
+                            const int at = 16 * cc + lr + 4 * r, bt = 16 * i + lc;
+                            if (bt < kb) {
+                                A[(int64_t)at * lda + bt] = 0.0;
+                                Linv[(int64_t)at * ldi + bt] = 0.0;
+                            }
+                        }
+                    });
+                }
+            });
+        });
     }
 }
 
-
-// Same factor + inverse with columns eliminated four at a time (fewer
-// barriers, more registers: used where no product kernel runs beside it).
+// Factor + inverse of one diagonal block held in registers element-wise,
+// columns eliminated four at a time (the persistent batched kernel's form).
 // Thread (ty, tx) of a 16 x 16 grid owns the elements (i, c) = (ty + 16a, tx + 16b)
 // with a >= b (the lower triangle, up to 36 per thread) in E[a][b] for the
 // whole kernel.  Columns are eliminated four at a time (J = j .. j+3), one
