@@ -204,7 +204,8 @@ def main():
         log(f"trace: {json.dumps(roof)}")
 
     cfg = {"workload": f"matern32-2d-n{n} factor+solves+logdet+adjoint", "n": n, "form": "fp64",
-           "block": args.block or 256, "lookahead": args.lookahead, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
+           "factor_block": args.block or (512 if n >= 8192 else 256), "adjoint_block": min(args.block or 256, 256),
+           "lookahead": args.lookahead, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
            "factor_residual_sampled": res_fact, "solve_eta_inf": eta64}
 
     if not args.headline_only:
@@ -245,6 +246,7 @@ def main():
         log(f"mixed: {msm:.2f} ms/step, {vm:.0f} GFLOP/s, refine iters {it} eta {etam:.2e}, "
             f"err vs fp64: L {eL:.2e} Abar {eA:.2e} alpha {ea:.2e}")
         cfg["mixed"] = {"value": round(vm, 2), "unit": "GFLOP/s", "ms_per_step": round(msm, 3),
+                        "factor_block": args.block or 256,
                         "speedup_vs_fp64": round(ms / msm, 3), "refine_iters": it, "refined_eta_inf": etam,
                         "phases_ms": phm, "classes_ms_per_step": trm,
                         "err_vs_fp64_path": {"L": eL, "Abar": eA, "alpha": ea},

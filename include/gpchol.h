@@ -55,7 +55,9 @@ typedef enum { GPC_NOTRANS = 0, GPC_TRANS = 1 } gpc_trans;
 
 typedef struct {
     int32_t precision;     /* gpc_precision; default GPC_FP64 */
-    int32_t block;         /* outer block size b of the blocked algorithms; 0 = library default */
+    int32_t block;         /* outer block size b of the blocked algorithms; 0 = library default
+                              (factor: 512 in FP64 from n = 8192 up, else 256; the adjoint
+                              uses min(block, 256), 256 by default) */
     int32_t lookahead;     /* 1 = overlap the next diagonal step with the trailing update */
     int32_t refine_maxit;  /* maximum refinement iterations of gpc_solve_refined (default 10) */
     double  refine_tol;    /* stop when the normwise backward error eta_inf <= refine_tol (default 1e-12) */
@@ -80,7 +82,7 @@ gpc_status gpc_destroy(gpc_handle* h);
 gpc_status gpc_set_stream(gpc_handle* h, void* hip_stream);
 
 /* Replace the handle's options (copied).  GPC_ERR_ARG on NULL, an unknown
- * precision, block not in {0, 32, 64, 128, 256}, refine_maxit < 0 or
+ * precision, block not in {0, 32, 64, 128, 256, 512}, refine_maxit < 0 or
  * refine_tol <= 0. */
 gpc_status gpc_set_options(gpc_handle* h, const gpc_options* opt);
 gpc_status gpc_get_options(const gpc_handle* h, gpc_options* opt);

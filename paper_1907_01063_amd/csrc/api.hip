@@ -184,6 +184,17 @@ hipEvent_t sync_event(gpc_handle* h, size_t i)
 
 int block_of(const gpc_handle* h) { return h->opt.block > 0 ? h->opt.block : kDefaultBlock; }
 
+// The factor's default outer block: 512 for the FP64 form of large matrices,
+// where the trailing update's K of 512 halves its passes over the trailing
+// matrix (the diagonal and panel work stays in 128-wide pieces).  The mixed
+// form keeps 256: its FP32 sums over K = 512 double the rounding the FP64
+// refinement of the solve then has to remove (one more sweep pair).
+int factor_block_of(const gpc_handle* h, int64_t n, bool mixed)
+{
+    if (h->opt.block > 0) return h->opt.block;
+    return !mixed && n >= 8192 ? 2 * kDefaultBlock : kDefaultBlock;
+}
+
 bool ld_ok(int64_t n, int64_t ld) { return ld >= std::max<int64_t>(1, n); }
 
 // Fixed split-K plan: about 512 workgroups per launch, at least 256 k-values
@@ -370,7 +381,8 @@ gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
 {
     if (!h || !o) return GPC_ERR_ARG;
     if (o->precision != GPC_FP64 && o->precision != GPC_MIXED) return GPC_ERR_ARG;
-    if (o->block != 0 && o->block != 32 && o->block != 64 && o->block != 128 && o->block != 256)
+    if (o->block != 0 && o->block != 32 && o->block != 64 && o->block != 128 && o->block != 256 &&
+        o->block != 512)
         return GPC_ERR_ARG;
     if (o->refine_maxit < 0 || !(o->refine_tol > 0.0)) return GPC_ERR_ARG;
     if (o->mixed_fallback != 0 && o->mixed_fallback != 1) return GPC_ERR_ARG;
@@ -386,12 +398,12 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* o)
 }
 
 // ---------------------------------------------------------------- factor ---
-// Right-looking blocked factorisation (section 3.3.1).  Outer block B (256 by
-// default) for the trailing update; within it, 128-wide halves: factor the
-// diagonal block and form its inverse (one workgroup), L21 = A21 inv(L11)^T
-// (MFMA product, in place), and update the next half's columns with the
-// first half's panel.  The trailing update A22 -= P P^T of outer step t is
-// split into the next outer block's columns ("narrow", main stream) and the
+// Right-looking blocked factorisation (section 3.3.1).  Outer block B (256,
+// or 512 for the FP64 form of large matrices, by default) for the trailing
+// update; within it, 128-wide pieces: factor the diagonal block and form its
+// inverse (one workgroup), L21 = A21 inv(L11)^T (MFMA product, in place), and
+// update the rest of the outer block's columns with the piece's panel.  The
+// trailing update A22 -= P P^T of outer step t is split into the next outer block's columns ("narrow", main stream) and the
 // rest ("big", lower tiles only).  With lookahead the big update of step t
 // runs on a second stream while step t+1's diagonal and panel work proceeds:
 //   main: wait big(t-2); panels(t); record panel(t); wait big(t-1); narrow(t)
@@ -407,7 +419,7 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
     hipStream_t s = h->stream;
     GPC_HIP(h, fill_i32(s, info, 0));
     if (n == 0) return GPC_OK;
-    const int B = block_of(h);
+    const int B = factor_block_of(h, n, mixed);
     const int ib = std::min(B, kDiagMax);
     const size_t n_linv = (size_t)ib * ib;
     const size_t n_pf = mixed ? 2 * (size_t)n * B : 0;
@@ -606,7 +618,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         return GPC_ERR_ARG;
     if (n == 0) return GPC_OK;
     hipStream_t s = h->stream;
-    const int b = block_of(h);
+    const int b = std::min(block_of(h), kDefaultBlock);   // the adjoint's blocks stop at 256
     const int64_t nblk = (n + b - 1) / b;
     const int kMaxSd = 64, kMaxSr = 32;
     const bool mixed = h->opt.precision == GPC_MIXED;

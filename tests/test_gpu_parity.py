@@ -171,7 +171,7 @@ def test_trsm_vector_and_logdet(H):
     assert abs(ld - oracle.logdet(Lo)) <= TOL * abs(oracle.logdet(Lo))
 
 
-@pytest.mark.parametrize("block,look", [(128, 0), (128, 1), (256, 0), (256, 1)])
+@pytest.mark.parametrize("block,look", [(128, 0), (128, 1), (256, 0), (256, 1), (512, 0), (512, 1)])
 @pytest.mark.parametrize("n", [300, 400, 1100, 1700])
 def test_blocking_and_lookahead_variants(H, block, look, n):
     # n = 300 / 400: ragged last 256-block with <= 128 / > 128 rows;
