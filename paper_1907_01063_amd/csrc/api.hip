@@ -403,8 +403,9 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* o)
 // update; within it, 128-wide pieces: factor the diagonal block and form its
 // inverse (one workgroup), L21 = A21 inv(L11)^T (MFMA product, in place), and
 // update the rest of the outer block's columns with the piece's panel.  The
-// trailing update A22 -= P P^T of outer step t is split into the next outer block's columns ("narrow", main stream) and the
-// rest ("big", lower tiles only).  With lookahead the big update of step t
+// trailing update A22 -= P P^T of outer step t is split into the next outer
+// block's columns ("narrow", main stream) and the rest ("big", lower tiles
+// only).  With lookahead the big update of step t
 // runs on a second stream while step t+1's diagonal and panel work proceeds:
 //   main: wait big(t-2); panels(t); record panel(t); wait big(t-1); narrow(t)
 //   side: wait panel(t); big(t); record big(t)
