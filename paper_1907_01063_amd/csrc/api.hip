@@ -197,18 +197,34 @@ int factor_block_of(const gpc_handle* h, int64_t n, bool mixed)
 
 bool ld_ok(int64_t n, int64_t ld) { return ld >= std::max<int64_t>(1, n); }
 
-// Fixed split-K plan: about 512 workgroups per launch, at least 256 k-values
-// per split, chunk a multiple of 32 (the largest BK).
-void splitk_plan(int64_t tiles, int64_t K, int max_splits, int* splits, int64_t* chunk)
+// Split-K plan: the split count s (at most max_splits, at least 256 k-values
+// per split, chunk a multiple of 32, the largest BK) that minimises the
+// launch's makespan: the number of rounds of `slots` co-resident workgroups
+// times the time of one workgroup (its chunk plus the partial slice it
+// writes), plus the reduction of the s slices.  Costs are in units of one
+// k-value of one 128 x 128 tile; a slice write counts 80 such units and its
+// reduction a third of a unit per tile and split.  A launch with a few
+// workgroups past a full round takes two rounds, which the plan avoids.
+void splitk_plan(int64_t tiles, int64_t K, int max_splits, int64_t slots, int* splits, int64_t* chunk)
 {
-    int64_t s = std::max<int64_t>(1, (512 + tiles - 1) / tiles);
-    s = std::min<int64_t>(s, std::max<int64_t>(1, K / 256));
-    s = std::min<int64_t>(s, max_splits);
-    int64_t c = (K + s - 1) / s;
-    c = (c + 31) / 32 * 32;
-    s = std::max<int64_t>(1, (K + c - 1) / c);
-    *splits = (int)s;
-    *chunk = c;
+    int64_t best_s = 1, best_c = std::max<int64_t>(32, (K + 31) / 32 * 32);
+    double best = -1.0;
+    for (int64_t s = 1; s <= max_splits; ++s) {
+        int64_t c = (K + s - 1) / s;
+        c = (c + 31) / 32 * 32;
+        if (s > 1 && c < 256) break;
+        const int64_t se = std::max<int64_t>(1, (K + c - 1) / c);
+        if (se != s) continue;                      // the same plan as a smaller s
+        const int64_t rounds = (tiles * se + slots - 1) / slots;
+        const double cost = (double)rounds * (double)(c + (se > 1 ? 80 : 0)) + (se > 1 ? 0.32 * tiles * se : 0.0);
+        if (best < 0.0 || cost < best) {
+            best = cost;
+            best_s = se;
+            best_c = c;
+        }
+    }
+    *splits = (int)best_s;
+    *chunk = best_c;
 }
 
 // Skinny products on the factor's critical path (the narrow updates, whose C
@@ -632,10 +648,10 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         const int64_t j = q * b, k = std::min<int64_t>(n, j + b), bq = k - j, K = bq + (n - k);
         const int64_t bn = std::min<int64_t>(b, j), jb = j - bn;
         int sr; int64_t ch;
-        splitk_plan(tiles128(bq, bn), K, kMaxSr, &sr, &ch);
+        splitk_plan(tiles128(bq, bn), K, kMaxSr, 2 * (int64_t)h->cus, &sr, &ch);
         prn_elems = std::max<int64_t>(prn_elems, (int64_t)sr * bq * bn);
         if (jb > 0) {
-            splitk_plan(tiles128(bq, jb), K, kMaxSr, &sr, &ch);
+            splitk_plan(tiles128(bq, jb), K, kMaxSr, 2 * (int64_t)h->cus, &sr, &ch);
             prb_elems = std::max<int64_t>(prb_elems, (int64_t)sr * bq * jb);
         }
     }
@@ -716,7 +732,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
                 }
             }
             int64_t ch;
-            splitk_plan(((bq + 63) / 64) * ((bq + 63) / 64), nr, kMaxSd, &sd, &ch);
+            splitk_plan(((bq + 63) / 64) * ((bq + 63) / 64), nr, kMaxSd, 4 * (int64_t)h->cus, &sd, &ch);
             Traced t(h, GPC_K_ADJ_DIAG_PRODUCT, 2.0 * dbq * dbq * dnr, 8.0 * (2.0 * dnr * dbq + sd * dbq * dbq));
             GemmArgs gd = gemm_args(bq, bq, nr, Cbar, ldlb, C, ldl, Pd, bq);
             gd.kchunk = ch;
@@ -761,7 +777,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
             if (nc <= 0) return GPC_OK;
             const double dnc = (double)nc;
             int sr; int64_t ch;
-            splitk_plan(tiles128(bq, nc), K, kMaxSr, &sr, &ch);
+            splitk_plan(tiles128(bq, nc), K, kMaxSr, 2 * (int64_t)h->cus, &sr, &ch);
             {
                 Traced t(h, GPC_K_ADJ_ROW_UPDATE, 2.0 * dbq * dnc * (double)K,
                          (mixed ? 4.0 : 8.0) * (double)K * (dbq + dnc) + 8.0 * sr * dbq * dnc, qs);

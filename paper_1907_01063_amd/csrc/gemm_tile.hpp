@@ -150,7 +150,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
             for (int p = 0; p < LA; ++p) {
                 const int kk = kA + p * ASTEP;
                 in[p] = (offA[p] != kOffOut) & (kk < krem) & !(alow & (dA - p * ASTEP > dmk));
-                oh[p] = in[p] & (kk < hrem) ? (uint32_t)(kk * g.ldah + mA) * (uint32_t)sizeof(TG) : kOffOut;
+                oh[p] = (in[p] & (kk < hrem)) ? (uint32_t)(kk * g.ldah + mA) * (uint32_t)sizeof(TG) : kOffOut;
             }
             if (hrem >= BK) {            // whole chunk in the head
 #pragma unroll
@@ -161,7 +161,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
 #pragma unroll
                 for (int p = 0; p < LA; ++p) {
                     const int kk = kA + p * ASTEP;
-                    const uint32_t om = in[p] & (kk >= hrem) ? (uint32_t)((kk - hrem) * g.lda + mA) * (uint32_t)sizeof(TG) : kOffOut;
+                    const uint32_t om = (in[p] & (kk >= hrem)) ? (uint32_t)((kk - hrem) * g.lda + mA) * (uint32_t)sizeof(TG) : kOffOut;
                     h[p] = (TI)buffer_ld<TG>(rh, oh[p]);
                     ra[p] = (TI)buffer_ld<TG>(rm, om);
                 }
@@ -356,7 +356,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                                                              0, 0, 0);
                 } else {
                     const int r = rr + 64 * h;
-                    const uint32_t off = (m0 + r < g.M) & (VE * pp < krem)
+                    const uint32_t off = ((m0 + r < g.M) & (VE * pp < krem))
                                              ? (uint32_t)(r * g.lda + VE * pp) * (uint32_t)sizeof(TG) : kOffOut;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Ap + m0 * g.lda + k0),
                                                              (lds_void*)(dA + (8 * wave + 64 * h) * BK), 16, off, 0, 0,
@@ -376,7 +376,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                                                              (lds_void*)(dB + kr * BN), 16, off, 0, 0, 0);
                 } else {
                     const int r = rr + 64 * h;
-                    const uint32_t off = (n0 + r < g.N) & (VE * pp < krem)
+                    const uint32_t off = ((n0 + r < g.N) & (VE * pp < krem))
                                              ? (uint32_t)(r * g.ldb + VE * pp) * (uint32_t)sizeof(TG) : kOffOut;
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(operand_rsrc(Bp + n0 * g.ldb + k0),
                                                              (lds_void*)(dB + (8 * wave + 64 * h) * BK), 16, off, 0, 0,
