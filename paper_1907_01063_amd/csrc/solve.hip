@@ -23,7 +23,11 @@ namespace {
 
 constexpr int kRhsGroup = 8;   // right-hand sides handled per launch
 constexpr int kSolveMax = 256; // largest block size of the sweeps
+
 constexpr int kRows = 64;      // rows per workgroup of the forward update
+
+// NRC: 1 for one right-hand side (the lookahead's operand rows are then
+// loaded before the wait for y and z), kRhsGroup otherwise.
 
 // rows [r0, r1): Y[r] -= L[r, j:j+BS] z (z in LDS).  TPR = BS/32 threads per
 // row, thread slot q covering columns q, q+TPR, ... (adjacent threads read
@@ -81,14 +85,19 @@ __device__ void bwd_cols(int64_t r0, int64_t r1, int64_t j, int bq, int nr, cons
         double v[TW];
 #pragma unroll
         for (int k = 0; k < TW; ++k) v[k] = t0 + k < bq ? L[(j + t0 + k) * ldl + r] : 0.0;
-        for (int c = 0; c < nr; ++c) {
-            double sacc = 0.0;
 #pragma unroll
-            for (int k = 0; k < TW; ++k) sacc += v[k] * z[t0 + k][c];
-            acc[c] = sacc;
+        for (int c = 0; c < kRhsGroup; ++c) {
+            if (c < nr) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int k = 0; k < TW; ++k) sacc += v[k] * z[t0 + k][c];
+                acc[c] = sacc;
+            }
         }
     }
-    for (int c = 0; c < nr; ++c) red[wave][lane][c] = acc[c];
+#pragma unroll
+    for (int c = 0; c < kRhsGroup; ++c)
+        if (c < nr) red[wave][lane][c] = acc[c];
     __syncthreads();
     if (wave == 0 && r < r1)
         for (int c = 0; c < nr; ++c)
@@ -151,6 +160,55 @@ __device__ void fwd_look(int i0, int bn, int bc, int nr, const double* Dn, const
         }
 }
 
+// Forward lookahead, one right-hand side: rows [i0, i0+16) of
+// z_next = Dinv y_next - Cf z_cur for the block [jn, jn + bn) (bn <= BS rows;
+// z_cur has bc entries, 0 if none).
+// 16 threads per row, thread slot s covers columns s, s+16, ...; the rows of
+// Dinv and Cf are loaded before y and z; the 16 partial sums of a row are
+// combined in a fixed order.
+template <int BS>
+__device__ void fwd_look1(int i0, int bn, int bc, int nr, const double* Dn, const double* Cf,
+                         const double* Y, int64_t jn, int64_t ldy, const double* zcur, double* znext, double* B,
+                         int64_t ldb)
+{
+    __shared__ double ys[BS][1];
+    __shared__ double zs[BS][1];
+    const int sl = threadIdx.x & 15;
+    const int i = i0 + (threadIdx.x >> 4);
+    double dv[BS / 16], cv[BS / 16];
+#pragma unroll
+    for (int m = 0; m < BS / 16; ++m) {
+        const int k = sl + 16 * m;
+        dv[m] = (i < bn && k <= i) ? Dn[(int64_t)i * BS + k] : 0.0;            // Dinv is lower
+        cv[m] = (i < bn && Cf && k < bc) ? Cf[(int64_t)i * BS + k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < BS * 1; e += 256) {
+        const int r = e / 1, c = e % 1;
+        ys[r][c] = (r < bn && c < nr) ? Y[(jn + r) * ldy + c] : 0.0;
+        zs[r][c] = (r < bc && c < nr) ? zcur[r * kRhsGroup + c] : 0.0;
+    }
+    __syncthreads();
+    double t[1];
+#pragma unroll
+    for (int c = 0; c < 1; ++c) {
+        t[c] = 0.0;
+#pragma unroll
+        for (int m = 0; m < BS / 16; ++m) t[c] += dv[m] * ys[sl + 16 * m][c] - cv[m] * zs[sl + 16 * m][c];
+    }
+#pragma unroll
+    for (int c = 0; c < 1; ++c) {
+#pragma unroll
+        for (int w = 1; w < 16; w <<= 1) {
+            const double o = __shfl_xor(t[c], w, 64);
+            t[c] = (sl & w) ? o + t[c] : t[c] + o;
+        }
+        if (sl == 0 && i < bn && c < nr) {
+            znext[i * kRhsGroup + c] = t[c];
+            B[(jn + i) * ldb + c] = t[c];
+        }
+    }
+}
+
 // Backward lookahead: rows [i0, i0+16) of x_prev = Dinv^T y_prev - Cb^T x_cur
 // for the block [jp, jp + bp) (x_cur has bc entries, 0 if none).  Thread
 // (t-slot g, row i0 + l) covers t = g, g+16, ...; partial sums over the 16
@@ -204,9 +262,57 @@ __device__ void bwd_look(int i0, int bp, int bc, int nr, const double* Dp, const
     }
 }
 
+// Backward lookahead, one right-hand side: rows [i0, i0+16) of
+// x_prev = Dinv^T y_prev - Cb^T x_cur for the block [jp, jp + bp) (x_cur has
+// bc entries, 0 if none).  Thread
+// (t-slot g, row i0 + l) covers t = g, g+16, ...; the columns of Dinv and Cb
+// are loaded before y and x; partial sums over the 16 t-slots are combined in
+// a fixed order through LDS.
+template <int BS>
+__device__ void bwd_look1(int i0, int bp, int bc, int nr, const double* Dp, const double* Cb,
+                         const double* Y, int64_t jp, int64_t ldy, const double* xcur, double* xnext, double* B,
+                         int64_t ldb)
+{
+    __shared__ double ys[BS][1];
+    __shared__ double xs[BS][1];
+    __shared__ double red[16][16][1];
+    const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int i = i0 + l;
+    double dv[BS / 16], cv[BS / 16];
+#pragma unroll
+    for (int m = 0; m < BS / 16; ++m) {
+        const int t = g + 16 * m;
+        dv[m] = (i < bp && t >= i && t < bp) ? Dp[(int64_t)t * BS + i] : 0.0;   // (Dinv^T)[i][t], Dinv lower
+        cv[m] = (i < bp && Cb && t < bc) ? Cb[(int64_t)t * BS + i] : 0.0;
+    }
+    for (int e = threadIdx.x; e < BS * 1; e += 256) {
+        const int r = e / 1, c = e % 1;
+        ys[r][c] = (r < bp && c < nr) ? Y[(jp + r) * ldy + c] : 0.0;
+        xs[r][c] = (r < bc && c < nr) ? xcur[r * kRhsGroup + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 1; ++c) {
+        double t2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < BS / 16; ++m) t2 += dv[m] * ys[g + 16 * m][c] - cv[m] * xs[g + 16 * m][c];
+        red[g][l][c] = t2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16 && i0 + (int)threadIdx.x < bp) {
+        const int ii = i0 + threadIdx.x;
+        for (int c = 0; c < nr; ++c) {
+            double v = 0.0;
+            for (int gg = 0; gg < 16; ++gg) v += red[gg][threadIdx.x][c];
+            xnext[ii * kRhsGroup + c] = v;
+            B[(jp + ii) * ldb + c] = v;
+        }
+    }
+}
+
 // Forward sweep, launch q (q = -1: z_0 only).  Workgroups < BS/16 form the
 // next block's z; the rest update the rows below the next block with z_q.
-template <int BS>
+template <int BS, int NRC>
 __global__ void __launch_bounds__(256)
 trsv_fwd(int64_t n, int nr, int64_t q, const double* L, int64_t ldl, const double* Dinv, const double* Cf,
          double* Y, int64_t ldy, const double* zcur, double* znext, double* B, int64_t ldb)
@@ -216,8 +322,12 @@ trsv_fwd(int64_t n, int nr, int64_t q, const double* L, int64_t ldl, const doubl
     const int bn = (int)min((int64_t)BS, n - jn);
     const int bc = q >= 0 ? BS : 0;                       // block q is full whenever a next block exists
     if (blockIdx.x < kLook) {
-        fwd_look<BS>(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * BS * BS,
-                     q >= 0 ? Cf + (q + 1) * BS * BS : nullptr, Y, jn, ldy, zcur, znext, B, ldb);
+        if constexpr (NRC == 1)
+            fwd_look1<BS>(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * BS * BS,
+                          q >= 0 ? Cf + (q + 1) * BS * BS : nullptr, Y, jn, ldy, zcur, znext, B, ldb);
+        else
+            fwd_look<BS>(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * BS * BS,
+                         q >= 0 ? Cf + (q + 1) * BS * BS : nullptr, Y, jn, ldy, zcur, znext, B, ldb);
     } else {
         __shared__ double z[BS][kRhsGroup];
         for (int e = threadIdx.x; e < BS * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
@@ -229,7 +339,7 @@ trsv_fwd(int64_t n, int nr, int64_t q, const double* L, int64_t ldl, const doubl
 
 // Backward sweep, launch q (q = nblk: x_{nblk-1} only): workgroups < BS/16
 // form x_{q-1}; the rest update the columns left of block q-1 with x_q.
-template <int BS>
+template <int BS, int NRC>
 __global__ void __launch_bounds__(256)
 trsv_bwd(int64_t n, int nr, int64_t q, int64_t nblk, const double* L, int64_t ldl, const double* Dinv,
          const double* Cb, double* Y, int64_t ldy, const double* xcur, double* xnext, double* B, int64_t ldb)
@@ -239,8 +349,12 @@ trsv_bwd(int64_t n, int nr, int64_t q, int64_t nblk, const double* L, int64_t ld
     const int bp = (int)min((int64_t)BS, n - jp);
     const int bc = q < nblk ? (int)min((int64_t)BS, n - q * BS) : 0;
     if (blockIdx.x < kLook) {
-        bwd_look<BS>(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * BS * BS,
-                     q < nblk ? Cb + (q - 1) * BS * BS : nullptr, Y, jp, ldy, xcur, xnext, B, ldb);
+        if constexpr (NRC == 1)
+            bwd_look1<BS>(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * BS * BS,
+                          q < nblk ? Cb + (q - 1) * BS * BS : nullptr, Y, jp, ldy, xcur, xnext, B, ldb);
+        else
+            bwd_look<BS>(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * BS * BS,
+                         q < nblk ? Cb + (q - 1) * BS * BS : nullptr, Y, jp, ldy, xcur, xnext, B, ldb);
     } else {
         __shared__ double z[BS][kRhsGroup];
         __shared__ double red[4][64][kRhsGroup];
@@ -357,15 +471,23 @@ hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double
                 const int64_t jn = (q + 1) * BS;
                 const int64_t rest = n - std::min(n, jn + BS);
                 const int64_t blocks = kLook + (q >= 0 ? (rest + kRows - 1) / kRows : 0);
-                hipLaunchKernelGGL((trsv_fwd<BS>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, L, ldl, Dinv,
-                                   Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
+                if (nr == 1)
+                    hipLaunchKernelGGL((trsv_fwd<BS, 1>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, L, ldl,
+                                       Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
+                else
+                    hipLaunchKernelGGL((trsv_fwd<BS, kRhsGroup>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q,
+                                       L, ldl, Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
             }
         } else {
             for (int64_t q = nblk; q >= 1; --q) {
                 const int64_t jp = (q - 1) * BS;
                 const int64_t blocks = kLook + (q < nblk ? (jp + 63) / 64 : 0);
-                hipLaunchKernelGGL((trsv_bwd<BS>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, nblk, L, ldl,
-                                   Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
+                if (nr == 1)
+                    hipLaunchKernelGGL((trsv_bwd<BS, 1>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, nblk, L,
+                                       ldl, Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
+                else
+                    hipLaunchKernelGGL((trsv_bwd<BS, kRhsGroup>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q,
+                                       nblk, L, ldl, Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
             }
         }
         hipError_t e = hipGetLastError();
