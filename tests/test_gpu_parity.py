@@ -142,7 +142,10 @@ def test_factor_then_adjoint_parity(H, kind, n):
     assert relf(host(Lbt), Ao) <= TOL
 
 
-@pytest.mark.parametrize("n", [1, 5, 128, 129, 300, 1000])
+# n = 511 / 512 / 513 / 767 / 1000: both sides of the switch from 128- to
+# 256-row sweep blocks, full and ragged last blocks; nrhs 1 takes the
+# one-column kernels, 3 and 9 the column-group ones (9: two groups)
+@pytest.mark.parametrize("n", [1, 5, 128, 129, 300, 511, 512, 513, 767, 1000])
 @pytest.mark.parametrize("nrhs", [1, 3, 9])
 def test_trsm_parity(H, n, nrhs):
     rng = np.random.default_rng(700 + n + nrhs)
