@@ -4,7 +4,10 @@
 // The solves sweep the b x b diagonal blocks of L (section 3.2 solves A x = b
 // through the inverse of the triangle; here only the diagonal blocks are
 // inverted, and the off-diagonal blocks are applied as matrix-vector
-// updates).  One launch per block step q, with lookahead: with the coupling
+// updates).  Several right-hand sides: one launch per block step q, with
+// lookahead (below); one right-hand side: the whole sweep in one launch whose
+// workgroups hand the blocks' solutions to each other (see the one-launch
+// sweeps further down).  Lookahead: with the coupling
 // blocks Cf_{q+1} = Dinv_{q+1} L_{q+1,q} formed beforehand, the next block's
 // solution is z_{q+1} = Dinv_{q+1} y_{q+1} - Cf_{q+1} z_q, where y_{q+1}
 // already holds the updates of all earlier blocks.  So in launch q a few
@@ -25,9 +28,6 @@ constexpr int kRhsGroup = 8;   // right-hand sides handled per launch
 constexpr int kSolveMax = 256; // largest block size of the sweeps
 
 constexpr int kRows = 64;      // rows per workgroup of the forward update
-
-// NRC: 1 for one right-hand side (the lookahead's operand rows are then
-// loaded before the wait for y and z), kRhsGroup otherwise.
 
 // rows [r0, r1): Y[r] -= L[r, j:j+BS] z (z in LDS).  TPR = BS/32 threads per
 // row, thread slot q covering columns q, q+TPR, ... (adjacent threads read
@@ -160,55 +160,6 @@ __device__ void fwd_look(int i0, int bn, int bc, int nr, const double* Dn, const
         }
 }
 
-// Forward lookahead, one right-hand side: rows [i0, i0+16) of
-// z_next = Dinv y_next - Cf z_cur for the block [jn, jn + bn) (bn <= BS rows;
-// z_cur has bc entries, 0 if none).
-// 16 threads per row, thread slot s covers columns s, s+16, ...; the rows of
-// Dinv and Cf are loaded before y and z; the 16 partial sums of a row are
-// combined in a fixed order.
-template <int BS>
-__device__ void fwd_look1(int i0, int bn, int bc, int nr, const double* Dn, const double* Cf,
-                         const double* Y, int64_t jn, int64_t ldy, const double* zcur, double* znext, double* B,
-                         int64_t ldb)
-{
-    __shared__ double ys[BS][1];
-    __shared__ double zs[BS][1];
-    const int sl = threadIdx.x & 15;
-    const int i = i0 + (threadIdx.x >> 4);
-    double dv[BS / 16], cv[BS / 16];
-#pragma unroll
-    for (int m = 0; m < BS / 16; ++m) {
-        const int k = sl + 16 * m;
-        dv[m] = (i < bn && k <= i) ? Dn[(int64_t)i * BS + k] : 0.0;            // Dinv is lower
-        cv[m] = (i < bn && Cf && k < bc) ? Cf[(int64_t)i * BS + k] : 0.0;
-    }
-    for (int e = threadIdx.x; e < BS * 1; e += 256) {
-        const int r = e / 1, c = e % 1;
-        ys[r][c] = (r < bn && c < nr) ? Y[(jn + r) * ldy + c] : 0.0;
-        zs[r][c] = (r < bc && c < nr) ? zcur[r * kRhsGroup + c] : 0.0;
-    }
-    __syncthreads();
-    double t[1];
-#pragma unroll
-    for (int c = 0; c < 1; ++c) {
-        t[c] = 0.0;
-#pragma unroll
-        for (int m = 0; m < BS / 16; ++m) t[c] += dv[m] * ys[sl + 16 * m][c] - cv[m] * zs[sl + 16 * m][c];
-    }
-#pragma unroll
-    for (int c = 0; c < 1; ++c) {
-#pragma unroll
-        for (int w = 1; w < 16; w <<= 1) {
-            const double o = __shfl_xor(t[c], w, 64);
-            t[c] = (sl & w) ? o + t[c] : t[c] + o;
-        }
-        if (sl == 0 && i < bn && c < nr) {
-            znext[i * kRhsGroup + c] = t[c];
-            B[(jn + i) * ldb + c] = t[c];
-        }
-    }
-}
-
 // Backward lookahead: rows [i0, i0+16) of x_prev = Dinv^T y_prev - Cb^T x_cur
 // for the block [jp, jp + bp) (x_cur has bc entries, 0 if none).  Thread
 // (t-slot g, row i0 + l) covers t = g, g+16, ...; partial sums over the 16
@@ -262,57 +213,9 @@ __device__ void bwd_look(int i0, int bp, int bc, int nr, const double* Dp, const
     }
 }
 
-// Backward lookahead, one right-hand side: rows [i0, i0+16) of
-// x_prev = Dinv^T y_prev - Cb^T x_cur for the block [jp, jp + bp) (x_cur has
-// bc entries, 0 if none).  Thread
-// (t-slot g, row i0 + l) covers t = g, g+16, ...; the columns of Dinv and Cb
-// are loaded before y and x; partial sums over the 16 t-slots are combined in
-// a fixed order through LDS.
-template <int BS>
-__device__ void bwd_look1(int i0, int bp, int bc, int nr, const double* Dp, const double* Cb,
-                         const double* Y, int64_t jp, int64_t ldy, const double* xcur, double* xnext, double* B,
-                         int64_t ldb)
-{
-    __shared__ double ys[BS][1];
-    __shared__ double xs[BS][1];
-    __shared__ double red[16][16][1];
-    const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
-    const int i = i0 + l;
-    double dv[BS / 16], cv[BS / 16];
-#pragma unroll
-    for (int m = 0; m < BS / 16; ++m) {
-        const int t = g + 16 * m;
-        dv[m] = (i < bp && t >= i && t < bp) ? Dp[(int64_t)t * BS + i] : 0.0;   // (Dinv^T)[i][t], Dinv lower
-        cv[m] = (i < bp && Cb && t < bc) ? Cb[(int64_t)t * BS + i] : 0.0;
-    }
-    for (int e = threadIdx.x; e < BS * 1; e += 256) {
-        const int r = e / 1, c = e % 1;
-        ys[r][c] = (r < bp && c < nr) ? Y[(jp + r) * ldy + c] : 0.0;
-        xs[r][c] = (r < bc && c < nr) ? xcur[r * kRhsGroup + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 1; ++c) {
-        double t2 = 0.0;
-#pragma unroll
-        for (int m = 0; m < BS / 16; ++m) t2 += dv[m] * ys[g + 16 * m][c] - cv[m] * xs[g + 16 * m][c];
-        red[g][l][c] = t2;
-    }
-    __syncthreads();
-    if (threadIdx.x < 16 && i0 + (int)threadIdx.x < bp) {
-        const int ii = i0 + threadIdx.x;
-        for (int c = 0; c < nr; ++c) {
-            double v = 0.0;
-            for (int gg = 0; gg < 16; ++gg) v += red[gg][threadIdx.x][c];
-            xnext[ii * kRhsGroup + c] = v;
-            B[(jp + ii) * ldb + c] = v;
-        }
-    }
-}
-
 // Forward sweep, launch q (q = -1: z_0 only).  Workgroups < BS/16 form the
 // next block's z; the rest update the rows below the next block with z_q.
-template <int BS, int NRC>
+template <int BS>
 __global__ void __launch_bounds__(256)
 trsv_fwd(int64_t n, int nr, int64_t q, const double* L, int64_t ldl, const double* Dinv, const double* Cf,
          double* Y, int64_t ldy, const double* zcur, double* znext, double* B, int64_t ldb)
@@ -322,12 +225,8 @@ trsv_fwd(int64_t n, int nr, int64_t q, const double* L, int64_t ldl, const doubl
     const int bn = (int)min((int64_t)BS, n - jn);
     const int bc = q >= 0 ? BS : 0;                       // block q is full whenever a next block exists
     if (blockIdx.x < kLook) {
-        if constexpr (NRC == 1)
-            fwd_look1<BS>(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * BS * BS,
-                          q >= 0 ? Cf + (q + 1) * BS * BS : nullptr, Y, jn, ldy, zcur, znext, B, ldb);
-        else
-            fwd_look<BS>(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * BS * BS,
-                         q >= 0 ? Cf + (q + 1) * BS * BS : nullptr, Y, jn, ldy, zcur, znext, B, ldb);
+        fwd_look<BS>(blockIdx.x * 16, bn, bc, nr, Dinv + (q + 1) * BS * BS,
+                     q >= 0 ? Cf + (q + 1) * BS * BS : nullptr, Y, jn, ldy, zcur, znext, B, ldb);
     } else {
         __shared__ double z[BS][kRhsGroup];
         for (int e = threadIdx.x; e < BS * kRhsGroup; e += 256) z[e / kRhsGroup][e % kRhsGroup] = zcur[e];
@@ -339,7 +238,7 @@ trsv_fwd(int64_t n, int nr, int64_t q, const double* L, int64_t ldl, const doubl
 
 // Backward sweep, launch q (q = nblk: x_{nblk-1} only): workgroups < BS/16
 // form x_{q-1}; the rest update the columns left of block q-1 with x_q.
-template <int BS, int NRC>
+template <int BS>
 __global__ void __launch_bounds__(256)
 trsv_bwd(int64_t n, int nr, int64_t q, int64_t nblk, const double* L, int64_t ldl, const double* Dinv,
          const double* Cb, double* Y, int64_t ldy, const double* xcur, double* xnext, double* B, int64_t ldb)
@@ -349,12 +248,8 @@ trsv_bwd(int64_t n, int nr, int64_t q, int64_t nblk, const double* L, int64_t ld
     const int bp = (int)min((int64_t)BS, n - jp);
     const int bc = q < nblk ? (int)min((int64_t)BS, n - q * BS) : 0;
     if (blockIdx.x < kLook) {
-        if constexpr (NRC == 1)
-            bwd_look1<BS>(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * BS * BS,
-                          q < nblk ? Cb + (q - 1) * BS * BS : nullptr, Y, jp, ldy, xcur, xnext, B, ldb);
-        else
-            bwd_look<BS>(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * BS * BS,
-                         q < nblk ? Cb + (q - 1) * BS * BS : nullptr, Y, jp, ldy, xcur, xnext, B, ldb);
+        bwd_look<BS>(blockIdx.x * 16, bp, bc, nr, Dinv + (q - 1) * BS * BS,
+                     q < nblk ? Cb + (q - 1) * BS * BS : nullptr, Y, jp, ldy, xcur, xnext, B, ldb);
     } else {
         __shared__ double z[BS][kRhsGroup];
         __shared__ double red[4][64][kRhsGroup];
@@ -387,9 +282,356 @@ __global__ void __launch_bounds__(256) logdet_kernel(int64_t n, const double* L,
     if (threadIdx.x == 0) *out = 2.0 * red[0];
 }
 
+// ---- one-launch sweeps, one right-hand side --------------------------------
+// The work of a sweep is cut into items handed out by a ticket counter in a
+// fixed order, one step at a time (forward: block q = 0, 1, ...; transposed:
+// q = nblk-1, nblk-2, ...), each step being the strips of block q and then
+// its chain items:
+//  - a strip item takes SR = 8192/BS rows (forward) or columns (transposed)
+//    of block q and forms y'_r = y_r - sum_p L_rp z_p (transposed: the L^T
+//    terms) over the blocks p two or more steps before q, one block at a time
+//    as each z_p is complete, then writes y' to the workspace;
+//  - a chain item forms 16 rows of the block's solution from y' and the
+//    solution of the step before through its coupling block (the lookahead
+//    formula of the launch-per-block sweep above).
+// An item only waits for items with smaller tickets and a ticket is only
+// taken by a running workgroup, so the sweep finishes whatever number of its
+// workgroups are resident.
+//
+// Hand-over.  y' and the solution are written to workspace vectors that
+// start filled with a signalling NaN, a value arithmetic never produces: the
+// chain items wait for their operands by reading them until none is that
+// value.  To keep that polling to the few items near the front of the sweep,
+// everything else waits on per-step counters (one word per workgroup) that
+// the chain items raise once their stores are complete: a chain item of step
+// q waits for step q-2 to be complete before it reads its operands, and the
+// strips wait on the counters for every block but their last (the one the
+// next chain item waits for), which they read like the chain items.  Every access of data written in the sweep is device-scope,
+// coherent across the per-XCD L2 caches by itself, so no cache maintenance
+// (L2 write-back or invalidate) is needed, and no plain load leaves a copy of
+// such data in an L2.  Every wait is bounded: after kSpinLimit polls the
+// sweep raises an error flag, later waits return at once and the chain items
+// write NaN, so a sweep that could not finish shows in its result.  The
+// reduction orders are fixed, so results repeat bit for bit.
+
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kCtrlStride = 32;                        // words between two counters (128 B)
+constexpr uint64_t kPending = 0x7FF0DEADBEEF0001ull;   // signalling NaN: not yet written
+
+// control words: [0] ticket, [kCtrlStride] error flag, then the counters of
+// the nblk steps
+__host__ __device__ constexpr int64_t ctrl_words(int64_t nblk) { return kCtrlStride * (nblk + 2); }
+__device__ __forceinline__ uint32_t* zdone(uint32_t* ctrl, int64_t q) { return ctrl + kCtrlStride * (2 + q); }
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of one thread: true while it may go on polling (the limit
+// raises the error flag; a raised flag ends every wait).
+__device__ __forceinline__ bool keep_polling(uint32_t& it, uint32_t* err)
+{
+    if ((++it & 255u) == 0) {
+        if (load_agent(err)) return false;
+        if (it >= kSpinLimit) {
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return true;
+}
+
+// One thread: *p once it is no longer kPending (or the sweep has failed).
+__device__ double await_value(const double* p, uint32_t* err)
+{
+    uint32_t it = 0;
+    double v = ld_dev(p);
+    while (__builtin_bit_cast(uint64_t, v) == kPending && keep_polling(it, err)) v = ld_dev(p);
+    return v;
+}
+
+// The counter work is done by the whole first wave, with values made uniform
+// by readfirstlane, so no branch around a barrier depends on the lane: a
+// branch on threadIdx.x == 0 at the end of the item loop lets the compiler
+// split the loop in two around it, thread 0 leaving the other lanes (still
+// cycling through the barriers) for the counter updates.
+__device__ __forceinline__ bool first_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0; }
+
+// All threads: returns once *ctr >= target (or the sweep has failed); loads
+// by ld_dev issued afterwards see the stores published before.
+__device__ void wait_count(const uint32_t* ctr, uint32_t target, uint32_t* err)
+{
+    if (first_wave()) {
+        uint32_t it = 0;
+        while (__builtin_amdgcn_readfirstlane(load_agent(ctr)) < target) {
+            if ((++it & 255u) == 0) {
+                if (__builtin_amdgcn_readfirstlane(load_agent(err))) break;
+                if (it >= kSpinLimit) {
+                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+}
+
+// All threads: waits for this workgroup's stores to complete, then adds one
+// to *ctr (lane 0 of the first wave adds 1, its other lanes 0).
+__device__ void publish(uint32_t* ctr)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (first_wave())
+        __hip_atomic_fetch_add(ctr, threadIdx.x == 0 ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Next item of this workgroup (all threads; uniform result).
+__device__ uint32_t next_ticket(uint32_t* ctrl)
+{
+    __shared__ uint32_t s_ticket;
+    if (first_wave()) {
+        const uint32_t v = __hip_atomic_fetch_add(ctrl, threadIdx.x == 0 ? 1u : 0u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        s_ticket = __builtin_amdgcn_readfirstlane(v);     // lane 0 holds the value before its add
+    }
+    __syncthreads();
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
+    __syncthreads();
+    return t;
+}
+
+// Forward strip: rows [q BS + r SR, +SR) of block q.  BS/32 threads per row,
+// slot s covering columns s, s + BS/32, ... of each block p; the slot sums
+// run over p in increasing order and are combined in a fixed tree.
+template <int BS>
+__device__ void fwd_strip(int64_t n, int64_t q, int r, const double* L, int64_t ldl, const double* B, int64_t ldb,
+                          const double* Zs, double* Yp, uint32_t* ctrl, double* zs)
+{
+    constexpr int TPR = BS / 32, SR = 256 / TPR, K = BS / 16;
+    const int slot = threadIdx.x % TPR;
+    const int64_t row = q * BS + (int64_t)r * SR + threadIdx.x / TPR;
+    const bool live = row < n;
+    double acc = 0.0;
+    for (int64_t p = 0; p + 2 <= q; ++p) {
+        double v[32];
+        const double* lr = L + (live ? row : 0) * ldl + p * BS + slot;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) v[k] = live ? lr[TPR * k] : 0.0;
+        if (p + 2 < q) {
+            wait_count(zdone(ctrl, p), K, ctrl + kCtrlStride);
+            if ((int)threadIdx.x < BS) zs[threadIdx.x] = ld_dev(Zs + p * BS + threadIdx.x);
+        } else if ((int)threadIdx.x < BS) {   // last block: on the chain's path, read as it lands
+            zs[threadIdx.x] = await_value(Zs + p * BS + threadIdx.x, ctrl + kCtrlStride);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 32; ++k) acc += v[k] * zs[slot + TPR * k];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int w = 1; w < TPR; w <<= 1) {
+        const double o = __shfl_xor(acc, w, 64);
+        acc = (slot & w) ? o + acc : acc + o;
+    }
+    if (slot == 0 && live) st_dev(Yp + row, ld_dev(B + row * ldb) - acc);
+}
+
+// Forward chain item c of block q: rows [16c, 16c+16) of
+// z_q = Dinv_q y'_q - Cf_q z_{q-1}, written to B and Zs.  16 threads per
+// row, slot s covering columns s, s+16, ...; the rows of Dinv_q and Cf_q are
+// loaded before the waits.
+template <int BS>
+__device__ void fwd_chain(int64_t n, int64_t q, int c, const double* Dinv, const double* Cf, double* B,
+                          int64_t ldb, double* Zs, const double* Yp, uint32_t* ctrl, double* ys, double* zs)
+{
+    const int bq = (int)min((int64_t)BS, n - q * BS);
+    const int sl = threadIdx.x & 15;
+    const int i = 16 * c + (int)(threadIdx.x >> 4);
+    const double* Dn = Dinv + q * BS * BS;
+    const double* Cn = Cf + q * BS * BS;
+    uint32_t* err = ctrl + kCtrlStride;
+    double dv[BS / 16], cv[BS / 16];
+#pragma unroll
+    for (int m = 0; m < BS / 16; ++m) {
+        const int k = sl + 16 * m;
+        dv[m] = (i < bq && k <= i) ? Dn[(int64_t)i * BS + k] : 0.0;   // Dinv is lower
+        cv[m] = (q >= 1 && i < bq) ? Cn[(int64_t)i * BS + k] : 0.0;
+    }
+    // until step q-2 is complete y'_q is far off: wait on its counter (one
+    // word per workgroup) before reading the data itself
+    if (q >= 2) wait_count(zdone(ctrl, q - 2), BS / 16, err);
+    if ((int)threadIdx.x < BS)
+        ys[threadIdx.x] = (int)threadIdx.x < bq ? await_value(Yp + q * BS + threadIdx.x, err) : 0.0;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int m = 0; m < BS / 16; ++m) t += dv[m] * ys[sl + 16 * m];
+    if (q >= 1) {
+        if ((int)threadIdx.x < BS) zs[threadIdx.x] = await_value(Zs + (q - 1) * BS + threadIdx.x, err);
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < BS / 16; ++m) t -= cv[m] * zs[sl + 16 * m];
+    }
+#pragma unroll
+    for (int w = 1; w < 16; w <<= 1) {
+        const double o = __shfl_xor(t, w, 64);
+        t = (sl & w) ? o + t : t + o;
+    }
+    if (sl == 0 && i < bq) {
+        const double z = load_agent(err) ? __builtin_nan("") : t;
+        st_dev(Zs + q * BS + i, z);
+        B[(q * BS + i) * ldb] = z;
+    }
+    publish(zdone(ctrl, q));
+}
+
+// Transposed strip: columns [q BS + r SR, +SR) of block q.  Thread (group g,
+// column j) covers rows g, g + 256/SR, ... of each block p below; the group
+// sums run over p in decreasing order and are combined in group order.
+template <int BS>
+__device__ void bwd_strip(int64_t n, int64_t nblk, int64_t q, int r, const double* L, int64_t ldl, const double* B,
+                          int64_t ldb, const double* Zs, double* Yp, uint32_t* ctrl, double* xs, double* red)
+{
+    constexpr int SR = 8192 / BS, NG = 256 / SR, K = BS / 16;
+    const int j = threadIdx.x % SR, g = threadIdx.x / SR;
+    const int64_t col = q * BS + (int64_t)r * SR + j;
+    const bool live = col < n;
+    double acc = 0.0;
+    for (int64_t p = nblk - 1; p >= q + 2; --p) {
+        const int bp = (int)min((int64_t)BS, n - p * BS);
+        double v[32];
+        const double* lc = L + (p * BS + g) * ldl + (live ? col : 0);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) v[k] = (live && g + NG * k < bp) ? lc[(int64_t)NG * k * ldl] : 0.0;
+        if (p > q + 2) {
+            wait_count(zdone(ctrl, p), K, ctrl + kCtrlStride);
+            if ((int)threadIdx.x < BS) xs[threadIdx.x] = (int)threadIdx.x < bp ? ld_dev(Zs + p * BS + threadIdx.x) : 0.0;
+        } else if ((int)threadIdx.x < BS) {   // last block: on the chain's path, read as it lands
+            xs[threadIdx.x] = (int)threadIdx.x < bp ? await_value(Zs + p * BS + threadIdx.x, ctrl + kCtrlStride) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 32; ++k) acc += v[k] * xs[g + NG * k];
+        __syncthreads();
+    }
+    red[threadIdx.x] = acc;                       // red[g * SR + j]
+    __syncthreads();
+    if (g == 0 && live) {
+        double sum = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < NG; ++gg) sum += red[gg * SR + j];
+        st_dev(Yp + col, ld_dev(B + col * ldb) - sum);
+    }
+}
+
+// Transposed chain item c of block q: rows [16c, 16c+16) of
+// x_q = Dinv_q^T y'_q - Cb_q^T x_{q+1}, written to B and Zs.  Thread
+// (t-slot g, row 16c + l) covers t = g, g+16, ...; the columns of Dinv_q and
+// Cb_q are loaded before the waits; the 16 t-slot sums are combined in slot
+// order.
+template <int BS>
+__device__ void bwd_chain(int64_t n, int64_t nblk, int64_t q, int c, const double* Dinv, const double* Cb, double* B,
+                          int64_t ldb, double* Zs, const double* Yp, uint32_t* ctrl, double* ys, double* xs,
+                          double* red)
+{
+    const int bq = (int)min((int64_t)BS, n - q * BS);
+    const int bc = q + 1 < nblk ? (int)min((int64_t)BS, n - (q + 1) * BS) : 0;
+    const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int i = 16 * c + l;
+    const double* Dp = Dinv + q * BS * BS;
+    const double* Cp = Cb + q * BS * BS;
+    uint32_t* err = ctrl + kCtrlStride;
+    double dv[BS / 16], cv[BS / 16];
+#pragma unroll
+    for (int m = 0; m < BS / 16; ++m) {
+        const int t = g + 16 * m;
+        dv[m] = (i < bq && t >= i && t < bq) ? Dp[(int64_t)t * BS + i] : 0.0;   // (Dinv^T)[i][t], Dinv lower
+        cv[m] = (i < bq && t < bc) ? Cp[(int64_t)t * BS + i] : 0.0;
+    }
+    if (q + 2 < nblk) wait_count(zdone(ctrl, q + 2), BS / 16, err);   // as in the forward chain
+    if ((int)threadIdx.x < BS)
+        ys[threadIdx.x] = (int)threadIdx.x < bq ? await_value(Yp + q * BS + threadIdx.x, err) : 0.0;
+    __syncthreads();
+    double part = 0.0;
+#pragma unroll
+    for (int m = 0; m < BS / 16; ++m) part += dv[m] * ys[g + 16 * m];
+    if (bc > 0) {
+        if ((int)threadIdx.x < BS)
+            xs[threadIdx.x] = (int)threadIdx.x < bc ? await_value(Zs + (q + 1) * BS + threadIdx.x, err) : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < BS / 16; ++m) part -= cv[m] * xs[g + 16 * m];
+    }
+    red[threadIdx.x] = part;                      // red[g * 16 + l]
+    __syncthreads();
+    if (threadIdx.x < 16 && 16 * c + (int)threadIdx.x < bq) {
+        double v = 0.0;
+        for (int gg = 0; gg < 16; ++gg) v += red[gg * 16 + threadIdx.x];
+        const double x = load_agent(err) ? __builtin_nan("") : v;
+        st_dev(Zs + q * BS + 16 * c + threadIdx.x, x);
+        B[(q * BS + 16 * c + threadIdx.x) * ldb] = x;
+    }
+    publish(zdone(ctrl, q));
+}
+
+// One launch of a whole sweep (trans 0: B <- L^-1 B, 1: B <- L^-T B) for one
+// right-hand side.  Yp, Zs: n doubles each, filled with kPending; ctrl:
+// ctrl_words(nblk) zeroed words.
+template <int BS, int TRANS>
+__global__ void __launch_bounds__(256, 4)
+trsv_sweep1(int64_t n, int64_t nblk, const double* L, int64_t ldl, const double* Dinv, const double* Cpl,
+            double* B, int64_t ldb, double* Yp, double* Zs, uint32_t* ctrl)
+{
+    constexpr int NS = BS * BS / 8192, K = BS / 16, P = NS + K;
+    __shared__ double s_a[BS], s_b[BS], s_red[256];
+    const uint32_t total = (uint32_t)(nblk * P);
+    for (;;) {
+        const uint32_t t = next_ticket(ctrl);
+        if (t >= total) break;
+        const int64_t step = t / P;
+        const int r = (int)(t % P);
+        const int64_t q = TRANS ? nblk - 1 - step : step;
+        if (!TRANS) {
+            if (r < NS) fwd_strip<BS>(n, q, r, L, ldl, B, ldb, Zs, Yp, ctrl, s_a);
+            else fwd_chain<BS>(n, q, r - NS, Dinv, Cpl, B, ldb, Zs, Yp, ctrl, s_a, s_b);
+        } else {
+            if (r < NS) bwd_strip<BS>(n, nblk, q, r, L, ldl, B, ldb, Zs, Yp, ctrl, s_a, s_red);
+            else bwd_chain<BS>(n, nblk, q, r - NS, Dinv, Cpl, B, ldb, Zs, Yp, ctrl, s_a, s_b, s_red);
+        }
+        // every item's lane-dependent tail joins here, so the loop has one
+        // back edge that all lanes take together
+        __syncthreads();
+    }
+}
+
+// Zeroes the control words and fills the 2n hand-over entries with kPending.
+__global__ void sweep_init(uint32_t* ctrl, int64_t words, double* V, int64_t count)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < words) ctrl[e] = 0u;
+    if (e < count) V[e] = __builtin_bit_cast(double, kPending);
+}
+
 }  // namespace
 
-int64_t trsm_workspace(int64_t n) { return (int64_t)kRhsGroup * n + 2 * kSolveMax * kRhsGroup; }
+// running right-hand sides, two z slots, then the control words of the
+// one-launch sweep (sized for the smallest block, 128)
+int64_t trsm_workspace(int64_t n)
+{
+    return (int64_t)kRhsGroup * n + 2 * kSolveMax * kRhsGroup + (ctrl_words((n + 127) / 128) + 1) / 2;
+}
 
 hipError_t trsm_couplings(hipStream_t s, int trans, int64_t n, const double* L, int64_t ldl, const double* Dinv,
                           int b, double* C)
@@ -453,9 +695,33 @@ hipError_t trsm_couplings(hipStream_t s, int trans, int64_t n, const double* L, 
 }
 
 namespace {
+// One right-hand side: fill the hand-over vectors and control words, then
+// one launch of at most four workgroups per compute unit.
+template <int BS>
+hipError_t sweep1(hipStream_t s, int trans, int64_t n, const double* L, int64_t ldl, const double* Dinv,
+                  const double* Cpl, double* B, int64_t ldb, double* Y, int cus)
+{
+    constexpr int P = BS * BS / 8192 + BS / 16;
+    const int64_t nblk = (n + BS - 1) / BS;
+    double* Yp = Y;                                   // y' (n), then the solution (n)
+    double* Zs = Y + n;
+    uint32_t* ctrl = (uint32_t*)(Y + (int64_t)kRhsGroup * n + 2 * kSolveMax * kRhsGroup);
+    const int64_t init = std::max<int64_t>(2 * n, ctrl_words(nblk));
+    hipLaunchKernelGGL(sweep_init, dim3((unsigned)((init + 255) / 256)), dim3(256), 0, s, ctrl, ctrl_words(nblk), Yp,
+                       2 * n);
+    const int64_t grid = std::min<int64_t>(nblk * P, 4 * (int64_t)std::max(cus, 1));
+    if (!trans)
+        hipLaunchKernelGGL((trsv_sweep1<BS, 0>), dim3((unsigned)grid), dim3(256), 0, s, n, nblk, L, ldl, Dinv, Cpl, B,
+                           ldb, Yp, Zs, ctrl);
+    else
+        hipLaunchKernelGGL((trsv_sweep1<BS, 1>), dim3((unsigned)grid), dim3(256), 0, s, n, nblk, L, ldl, Dinv, Cpl, B,
+                           ldb, Yp, Zs, ctrl);
+    return hipGetLastError();
+}
+
 template <int BS>
 hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
-                 const double* Dinv, const double* Cpl, double* B, int64_t ldb, double* Y)
+                 const double* Dinv, const double* Cpl, double* B, int64_t ldb, double* Y, int cus)
 {
     constexpr int kLook = BS / 16;
     const int64_t nblk = (n + BS - 1) / BS;
@@ -464,6 +730,11 @@ hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double
     for (int64_t c0 = 0; c0 < nrhs; c0 += kRhsGroup) {
         const int nr = (int)std::min<int64_t>(kRhsGroup, nrhs - c0);
         double* Bc = B + c0;
+        if (nr == 1) {
+            const hipError_t e = sweep1<BS>(s, trans, n, L, ldl, Dinv, Cpl, Bc, ldb, Y, cus);
+            if (e != hipSuccess) return e;
+            continue;
+        }
         hipLaunchKernelGGL(copy_cols, dim3((unsigned)((n * nr + 255) / 256)), dim3(256), 0, s, n, nr, Bc, ldb, Y,
                            (int64_t)kRhsGroup);
         if (!trans) {
@@ -471,23 +742,15 @@ hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double
                 const int64_t jn = (q + 1) * BS;
                 const int64_t rest = n - std::min(n, jn + BS);
                 const int64_t blocks = kLook + (q >= 0 ? (rest + kRows - 1) / kRows : 0);
-                if (nr == 1)
-                    hipLaunchKernelGGL((trsv_fwd<BS, 1>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, L, ldl,
-                                       Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
-                else
-                    hipLaunchKernelGGL((trsv_fwd<BS, kRhsGroup>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q,
-                                       L, ldl, Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
+                hipLaunchKernelGGL((trsv_fwd<BS>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, L, ldl, Dinv,
+                                   Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q + 1), Bc, ldb);
             }
         } else {
             for (int64_t q = nblk; q >= 1; --q) {
                 const int64_t jp = (q - 1) * BS;
                 const int64_t blocks = kLook + (q < nblk ? (jp + 63) / 64 : 0);
-                if (nr == 1)
-                    hipLaunchKernelGGL((trsv_bwd<BS, 1>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, nblk, L,
-                                       ldl, Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
-                else
-                    hipLaunchKernelGGL((trsv_bwd<BS, kRhsGroup>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q,
-                                       nblk, L, ldl, Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
+                hipLaunchKernelGGL((trsv_bwd<BS>), dim3((unsigned)blocks), dim3(256), 0, s, n, nr, q, nblk, L, ldl,
+                                   Dinv, Cpl, Y, (int64_t)kRhsGroup, zslot(q), zslot(q - 1), Bc, ldb);
             }
         }
         hipError_t e = hipGetLastError();
@@ -498,10 +761,10 @@ hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double
 }  // namespace
 
 hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
-                        const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb, double* Y)
+                        const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb, double* Y, int cus)
 {
-    if (b == 128) return sweep<128>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y);
-    if (b == 256) return sweep<256>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y);
+    if (b == 128) return sweep<128>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus);
+    if (b == 256) return sweep<256>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus);
     return hipErrorInvalidValue;
 }
 
