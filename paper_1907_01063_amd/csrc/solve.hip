@@ -352,12 +352,19 @@ __device__ __forceinline__ bool keep_polling(uint32_t& it, uint32_t* err)
 }
 
 // One thread: *p once it is no longer kPending (or the sweep has failed).
+// Two reads are kept in flight, the older one checked while the newer is on
+// its way, so a value is seen about half a round trip sooner than with one.
 __device__ double await_value(const double* p, uint32_t* err)
 {
     uint32_t it = 0;
-    double v = ld_dev(p);
-    while (__builtin_bit_cast(uint64_t, v) == kPending && keep_polling(it, err)) v = ld_dev(p);
-    return v;
+    double a = ld_dev(p);
+    double b = ld_dev(p);
+    for (;;) {
+        if (__builtin_bit_cast(uint64_t, a) != kPending || !keep_polling(it, err)) return a;
+        a = ld_dev(p);
+        if (__builtin_bit_cast(uint64_t, b) != kPending || !keep_polling(it, err)) return b;
+        b = ld_dev(p);
+    }
 }
 
 // The counter work is done by the whole first wave, with values made uniform
@@ -423,6 +430,9 @@ __device__ void fwd_strip(int64_t n, int64_t q, int r, const double* L, int64_t 
     const int slot = threadIdx.x % TPR;
     const int64_t row = q * BS + (int64_t)r * SR + threadIdx.x / TPR;
     const bool live = row < n;
+    // y_row is only overwritten (by the solution) after this strip's y' is
+    // read, so it is loaded first, off the path of the last block
+    const double yv = (slot == 0 && live) ? ld_dev(B + row * ldb) : 0.0;
     double acc = 0.0;
     for (int64_t p = 0; p + 2 <= q; ++p) {
         double v[32];
@@ -445,7 +455,7 @@ __device__ void fwd_strip(int64_t n, int64_t q, int r, const double* L, int64_t 
         const double o = __shfl_xor(acc, w, 64);
         acc = (slot & w) ? o + acc : acc + o;
     }
-    if (slot == 0 && live) st_dev(Yp + row, ld_dev(B + row * ldb) - acc);
+    if (slot == 0 && live) st_dev(Yp + row, yv - acc);
 }
 
 // Forward chain item c of block q: rows [16c, 16c+16) of
@@ -508,6 +518,7 @@ __device__ void bwd_strip(int64_t n, int64_t nblk, int64_t q, int r, const doubl
     const int j = threadIdx.x % SR, g = threadIdx.x / SR;
     const int64_t col = q * BS + (int64_t)r * SR + j;
     const bool live = col < n;
+    const double yv = (g == 0 && live) ? ld_dev(B + col * ldb) : 0.0;   // as in the forward strip
     double acc = 0.0;
     for (int64_t p = nblk - 1; p >= q + 2; --p) {
         const int bp = (int)min((int64_t)BS, n - p * BS);
@@ -532,7 +543,7 @@ __device__ void bwd_strip(int64_t n, int64_t nblk, int64_t q, int r, const doubl
         double sum = 0.0;
 #pragma unroll
         for (int gg = 0; gg < NG; ++gg) sum += red[gg * SR + j];
-        st_dev(Yp + col, ld_dev(B + col * ldb) - sum);
+        st_dev(Yp + col, yv - sum);
     }
 }
 

@@ -144,7 +144,8 @@ def test_factor_then_adjoint_parity(H, kind, n):
 
 # n = 511 / 512 / 513 / 767 / 1000: both sides of the switch from 128- to
 # 256-row sweep blocks, full and ragged last blocks; nrhs 1 takes the
-# one-column kernels, 3 and 9 the column-group ones (9: two groups)
+# one-launch sweep, 3 and 9 the column-group launches (9: a group of 8, then
+# its last column through the one-launch sweep)
 @pytest.mark.parametrize("n", [1, 5, 128, 129, 300, 511, 512, 513, 767, 1000])
 @pytest.mark.parametrize("nrhs", [1, 3, 9])
 def test_trsm_parity(H, n, nrhs):
@@ -157,6 +158,27 @@ def test_trsm_parity(H, n, nrhs):
         Bt = dev(B)
         H.trsm(Lt, Bt, trans=trans)
         assert relf(host(Bt), oracle.trsm(L0, B, trans=trans)) <= TOL
+
+
+# one-launch sweep: a column of a wider matrix (leading dimension 5) at sizes
+# with several blocks and a ragged last block; repeated calls agree bit for bit
+@pytest.mark.parametrize("n", [2000, 4100])
+def test_trsm_one_column_strided_repeatable(H, n):
+    rng = np.random.default_rng(900 + n)
+    _, L0 = W.spd_from_factor(rng, n)
+    B = rng.standard_normal((n, 5))
+    say(f"trsm one column n={n}")
+    Lt = dev(L0)
+    for trans in (False, True):
+        outs = []
+        for _ in range(2):
+            Bt = dev(B)
+            H.trsm(Lt, Bt[:, 2:3], trans=trans)
+            outs.append(host(Bt))
+        assert np.array_equal(outs[0], outs[1])
+        assert np.array_equal(np.delete(outs[0], 2, axis=1), np.delete(B, 2, axis=1))   # other columns untouched
+        assert relf(outs[0][:, 2:3], oracle.trsm(L0, B[:, 2:3], trans=trans)) <= TOL
+        assert not np.isnan(outs[0]).any()
 
 
 def test_trsm_vector_and_logdet(H):
