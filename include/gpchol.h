@@ -116,7 +116,10 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl,
 
 /* Triangular solve with the factor (section 3.2, A x = b with A triangular):
  * B <- L^-1 B (trans = GPC_NOTRANS) or B <- L^-T B (GPC_TRANS).
- * B is n x nrhs row-major with leading dimension ldb >= max(1, nrhs). */
+ * B is n x nrhs row-major with leading dimension ldb >= max(1, nrhs).
+ * A single column is solved in one launch whose workgroups wait on each
+ * other with bounded waits; were a wait ever to run out, the entries it
+ * guards would be NaN (the call itself cannot report it). */
 gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs,
                     const double* L, int64_t ldl, double* B, int64_t ldb);
 

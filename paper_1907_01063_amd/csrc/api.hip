@@ -938,20 +938,20 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
     const int64_t nblk = (n + b - 1) / b;
     const size_t n_dinv = (size_t)nblk * b * b;
     const size_t n_part = (size_t)symv_parts(n);
-    gpc_status st = ensure_ws(h, sizeof(double) * (3 * n_dinv + (size_t)trsm_workspace(n) + n_part + 3 * (size_t)n));
+    gpc_status st =
+        ensure_ws(h, sizeof(double) * (3 * n_dinv + (size_t)trsm_workspace(n) + 2 * n_part + 3 * (size_t)n));
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
     double* Cf = Dinv + n_dinv;
     double* Cb = Cf + n_dinv;
     double* Y = Cb + n_dinv;
     double* part = Y + trsm_workspace(n);
-    double* rowabs = part + n_part;
+    double* rowabs = part + 2 * n_part;
     double* r = rowabs + n;
     double* d = r + n;
     GPC_HIP(h, diag_block_inverses(s, n, b, L, ldl, Dinv, Cf));
     GPC_HIP(h, trsm_couplings(s, 0, n, L, ldl, Dinv, b, Cf));
     GPC_HIP(h, trsm_couplings(s, 1, n, L, ldl, Dinv, b, Cb));
-    GPC_HIP(h, symv_lower(s, n, K, ldk, nullptr, 1, nullptr, 1.0, rowabs, part));
     GPC_HIP(h, vec_zero(s, n, x));
     GPC_HIP(h, vec_copy(s, n, y, r));
     const int maxit = std::max(1, h->opt.refine_maxit);
@@ -963,7 +963,10 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
         GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, d, 1, Y, h->cus));
         GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, d, 1, Y, h->cus));
         GPC_HIP(h, vec_axpy(s, n, d, x));
-        GPC_HIP(h, symv_lower(s, n, K, ldk, x, 0, y, -1.0, r, part));
+        if (it == 1)   // the row sums of |K| for eta come from the same pass over K
+            GPC_HIP(h, symv_lower_abs(s, n, K, ldk, x, y, -1.0, r, rowabs, part));
+        else
+            GPC_HIP(h, symv_lower(s, n, K, ldk, x, 0, y, -1.0, r, part));
         GPC_HIP(h, refine_eta(s, n, r, x, y, rowabs, eta));
         GPC_HIP(h, hipMemcpyAsync(&eta_h, eta, sizeof(double), hipMemcpyDeviceToHost, s));
         GPC_HIP(h, hipStreamSynchronize(s));

@@ -172,9 +172,12 @@ gp_value_kernel(int64_t n, const double* z, const double* logdet, double* f)
 // SYMV partials: workgroup per lower 64 x 64 block (bi, bj).  With the
 // symmetric block S (lower-stored; the diagonal block mirrored),
 // part[bi][bj] = S x[bj] and, off the diagonal, part[bj][bi] = S^T x[bi].
-// absk: use |S|; x == nullptr: x is all ones.
+// absk: use |S|; x == nullptr: x is all ones.  part2 (if not null) also
+// gets the same partials of |S| times a vector of ones (the row sums of |K|
+// in the same pass over K).
 __global__ void __launch_bounds__(256)
-symv_blocks(int64_t n, const double* K, int64_t ldk, const double* x, int absk, double* part, int64_t nb)
+symv_blocks(int64_t n, const double* K, int64_t ldk, const double* x, int absk, double* part, double* part2,
+            int64_t nb)
 {
     __shared__ double S[kS][kS + 1];
     __shared__ double xr[kS], xc[kS], pr[4][kS], pc[4][kS];
@@ -185,15 +188,23 @@ symv_blocks(int64_t n, const double* K, int64_t ldk, const double* x, int absk, 
     const int64_t bj = t - bi * (bi + 1) / 2;
     const int64_t i0 = bi * kS, j0 = bj * kS;
     const int tid = threadIdx.x;
-    for (int e = tid; e < kS * kS; e += 256) {
-        const int r = e / kS, c = e % kS;
-        const int64_t i = i0 + r, j = j0 + c;
-        double v = 0.0;
-        if (i < n && j < n) {
-            if (bi != bj || j <= i) v = K[i * ldk + j];
-            else v = K[j * ldk + i];
+    // lane c of wave w takes column c of rows w, w+4, ...: all 16 loads are
+    // issued before the first is stored (the upper part of a diagonal block
+    // is read from its mirror)
+    {
+        constexpr int R = kS * kS / 256;
+        const int c = tid % kS, rw = tid / kS;
+        const int64_t j = j0 + c;
+        double v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int64_t i = i0 + rw + 4 * k;
+            const bool up = bi == bj && j > i;
+            const int64_t off = up ? j * ldk + i : i * ldk + j;
+            v[k] = (i < n && j < n) ? K[off] : 0.0;
         }
-        S[r][c] = absk ? fabs(v) : v;
+#pragma unroll
+        for (int k = 0; k < R; ++k) S[rw + 4 * k][c] = absk ? fabs(v[k]) : v[k];
     }
     if (tid < kS) {
         const int64_t j = j0 + tid, i = i0 + tid;
@@ -202,10 +213,14 @@ symv_blocks(int64_t n, const double* K, int64_t ldk, const double* x, int absk, 
     }
     __syncthreads();
     const int row = tid & 63, part4 = tid >> 6;
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, a2 = 0.0, b2 = 0.0;
     for (int c = part4 * 16; c < part4 * 16 + 16; ++c) {
         a += S[row][c] * xc[c];   // (S x_c)[row]
         b += S[c][row] * xr[c];   // (S^T x_r)[row]
+        if (part2) {              // entries outside K are zero in S
+            a2 += fabs(S[row][c]);
+            b2 += fabs(S[c][row]);
+        }
     }
     pr[part4][row] = a;
     pc[part4][row] = b;
@@ -214,17 +229,43 @@ symv_blocks(int64_t n, const double* K, int64_t ldk, const double* x, int absk, 
         part[(bi * nb + bj) * kS + tid] = ((pr[0][tid] + pr[1][tid]) + pr[2][tid]) + pr[3][tid];
         if (bi != bj) part[(bj * nb + bi) * kS + tid] = ((pc[0][tid] + pc[1][tid]) + pc[2][tid]) + pc[3][tid];
     }
+    if (part2) {
+        __syncthreads();
+        pr[part4][row] = a2;
+        pc[part4][row] = b2;
+        __syncthreads();
+        if (tid < kS) {
+            part2[(bi * nb + bj) * kS + tid] = ((pr[0][tid] + pr[1][tid]) + pr[2][tid]) + pr[3][tid];
+            if (bi != bj) part2[(bj * nb + bi) * kS + tid] = ((pc[0][tid] + pc[1][tid]) + pc[2][tid]) + pc[3][tid];
+        }
+    }
 }
 
-// out[i] = (y ? y[i] : 0) + sgn * sum_s part[i/64][s][i%64]  (s increasing)
-__global__ void symv_finish(int64_t n, int64_t nb, const double* part, const double* y, double sgn, double* out)
+// out[i] = (y ? y[i] : 0) + sgn * sum_s part[i/64][s][i%64]: one workgroup
+// per 64 rows, the nb partial sums of a row split into four consecutive
+// ranges (s increasing within each, loads issued eight at a time) that are
+// then added in range order.
+__global__ void __launch_bounds__(256)
+symv_finish(int64_t n, int64_t nb, const double* part, const double* y, double sgn, double* out)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const int64_t bi = i / kS, r = i % kS;
+    __shared__ double red[4][kS];
+    const int r = threadIdx.x % kS, g = threadIdx.x / kS;
+    const int64_t bi = blockIdx.x, i = bi * kS + r;
+    const int64_t per = (nb + 3) / 4, t0 = g * per, t1 = min(nb, t0 + per);
+    const double* p = part + (bi * nb) * kS + r;
     double s = 0.0;
-    for (int64_t t = 0; t < nb; ++t) s += part[(bi * nb + t) * kS + r];
-    out[i] = (y ? y[i] : 0.0) + sgn * s;
+    int64_t t = t0;
+    for (; t + 8 <= t1; t += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = p[(t + k) * kS];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; t < t1; ++t) s += p[t * kS];
+    red[g][r] = s;
+    __syncthreads();
+    if (g == 0 && i < n) out[i] = (y ? y[i] : 0.0) + sgn * (((red[0][r] + red[1][r]) + red[2][r]) + red[3][r]);
 }
 
 __global__ void __launch_bounds__(256)
@@ -327,8 +368,22 @@ hipError_t symv_lower(hipStream_t s, int64_t n, const double* K, int64_t ldk, co
     if (n <= 0) return hipSuccess;
     const int64_t nb = (n + kS - 1) / kS;
     hipLaunchKernelGGL(symv_blocks, dim3((unsigned)(nb * (nb + 1) / 2)), dim3(256), 0, s, n, K, ldk, x, absk,
-                       part, nb);
-    hipLaunchKernelGGL(symv_finish, dim3(blocks256(n)), dim3(256), 0, s, n, nb, part, y, sgn, out);
+                       part, (double*)nullptr, nb);
+    hipLaunchKernelGGL(symv_finish, dim3((unsigned)nb), dim3(256), 0, s, n, nb, part, y, sgn, out);
+    return hipGetLastError();
+}
+
+hipError_t symv_lower_abs(hipStream_t s, int64_t n, const double* K, int64_t ldk, const double* x, const double* y,
+                          double sgn, double* out, double* rowabs, double* part)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kS - 1) / kS;
+    double* part2 = part + symv_parts(n);
+    hipLaunchKernelGGL(symv_blocks, dim3((unsigned)(nb * (nb + 1) / 2)), dim3(256), 0, s, n, K, ldk, x, 0, part,
+                       part2, nb);
+    hipLaunchKernelGGL(symv_finish, dim3((unsigned)nb), dim3(256), 0, s, n, nb, part, y, sgn, out);
+    hipLaunchKernelGGL(symv_finish, dim3((unsigned)nb), dim3(256), 0, s, n, nb, part2, (const double*)nullptr, 1.0,
+                       rowabs);
     return hipGetLastError();
 }
 

@@ -115,6 +115,10 @@ int64_t symv_parts(int64_t n);                  // doubles of workspace for symv
 // out = y + sgn * K x  (K symmetric from its lower triangle; absk: |K|; x null: ones; y null: 0)
 hipError_t symv_lower(hipStream_t s, int64_t n, const double* K, int64_t ldk, const double* x, int absk,
                       const double* y, double sgn, double* out, double* part);
+// The same with x given, and in the same pass rowabs = |K| times ones (the row
+// sums of |K|); part: 2 symv_parts(n) doubles.
+hipError_t symv_lower_abs(hipStream_t s, int64_t n, const double* K, int64_t ldk, const double* x, const double* y,
+                          double sgn, double* out, double* rowabs, double* part);
 hipError_t refine_eta(hipStream_t s, int64_t n, const double* r, const double* x, const double* y,
                       const double* rowabs, double* eta);
 hipError_t vec_axpy(hipStream_t s, int64_t n, const double* d, double* x);
