@@ -105,9 +105,22 @@ __device__ void adjoint_one(int n, int b, const double* L, double* Lb, const Scr
                                                    lds);
         }
         // W = tril(Dbar - Cbar^T C)
-        for (int e = threadIdx.x; e < bq * bq; e += 256) {
-            const int r = e / bq, c = e % bq;
-            w.W[r * kBB + c] = r >= c ? Dbar[r * ld + c] - (nr > 0 ? w.P[r * kBB + c] : 0.0) : 0.0;
+        for (int base = 0; base < bq * bq; base += 16 * 256) {   // 16 loads per thread in flight
+            double dv[16], pv[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int e = base + threadIdx.x + 256 * k;
+                const int r = e / bq, c = e % bq;
+                const bool in = e < bq * bq && r >= c;
+                dv[k] = in ? Dbar[r * ld + c] : 0.0;
+                pv[k] = in && nr > 0 ? w.P[r * kBB + c] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int e = base + threadIdx.x + 256 * k;
+                const int r = e / bq, c = e % bq;
+                if (e < bq * bq) w.W[r * kBB + c] = r >= c ? dv[k] - pv[k] : 0.0;
+            }
         }
         __syncthreads();
         GemmArgs gp = ga(bq, bq, bq, D, ld, w.W, kBB, w.S, kBB);

@@ -582,10 +582,24 @@ __device__ void diag_inverse(int kb, const double* L, int64_t ldl, double* X, in
 {
     constexpr int P = 16 * NA + 1;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-    for (int idx = tid; idx < kb * kb; idx += 256) {
-        const int r = idx / kb, c = idx % kb;
-        Ls[r * P + c] = c <= r ? L[r * ldl + c] : 0.0;
-        if (c > r) X[r * ldx + c] = 0.0;
+    // 16 loads per thread issued before their stores to LDS
+    for (int base = 0; base < kb * kb; base += 16 * 256) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int idx = base + tid + 256 * k;
+            const int r = idx / kb, c = idx % kb;
+            v[k] = (idx < kb * kb && c <= r) ? L[r * ldl + c] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int idx = base + tid + 256 * k;
+            const int r = idx / kb, c = idx % kb;
+            if (idx < kb * kb) {
+                Ls[r * P + c] = v[k];
+                if (c > r) X[r * ldx + c] = 0.0;
+            }
+        }
     }
     double E[NA][NA];
 #pragma unroll

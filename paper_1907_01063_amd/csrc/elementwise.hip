@@ -33,15 +33,31 @@ __global__ void convert_lower_kernel(int64_t n, const double* L, int64_t ldl, fl
     if (r < n && c < r) Lf[r * ldf + c] = (float)L[r * ldl + c];
 }
 
+// sum_{z<S} p[z * pstride] with z increasing, the loads issued sixteen at a
+// time (the additions keep that order, so the result does not depend on the
+// batching).
+__device__ __forceinline__ double slice_sum(const double* p, int S, int64_t pstride)
+{
+    constexpr int G = 16;
+    double s = 0.0;
+    for (int z = 0; z < S; z += G) {
+        double v[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) v[k] = z + k < S ? p[(int64_t)(z + k) * pstride] : 0.0;
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (z + k < S) s += v[k];
+    }
+    return s;
+}
+
 __global__ void reduce_sub_kernel(int64_t M, int64_t N, const double* P, int S, int64_t pstride,
                                   double* C, int64_t ldc)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= M * N) return;
     const int64_t m = e / N, n = e % N;
-    double s = 0.0;
-    for (int z = 0; z < S; ++z) s += P[z * pstride + m * N + n];
-    C[m * ldc + n] -= s;
+    C[m * ldc + n] -= slice_sum(P + m * N + n, S, pstride);
 }
 
 __global__ void reduce_tril_kernel(int b, const double* D, int64_t ldd, const double* P, int S,
@@ -51,11 +67,7 @@ __global__ void reduce_tril_kernel(int b, const double* D, int64_t ldd, const do
     if (e >= b * b) return;
     const int m = e / b, n = e % b;
     double v = 0.0;
-    if (m >= n) {
-        double s = 0.0;
-        for (int z = 0; z < S; ++z) s += P[z * pstride + (int64_t)m * b + n];
-        v = D[m * ldd + n] - s;
-    }
+    if (m >= n) v = D[m * ldd + n] - slice_sum(P + (int64_t)m * b + n, S, pstride);
     W[e] = v;
 }
 
