@@ -94,6 +94,14 @@ def test_refined_solve_reports_nonconvergence(H):
         assert ei.value.status == GPC_ERR_REFINE
         x, iters, eta = H.solve_refined(dev(case["A"]), L, dev(case["y"]), check=False)
         assert int(host(iters)) == 1
+        # after one step with the mixed factor the residual is far above
+        # rounding, so eta (and the row sums of |K| it uses, formed in the
+        # same pass as the residual) can be checked against its definition
+        A, yv, xv = case["A"], case["y"], host(x)
+        r = yv - A @ xv
+        eta_h = np.abs(r).max() / (np.abs(A).sum(axis=1).max() * np.abs(xv).max() + np.abs(yv).max())
+        assert eta_h > 1e-13
+        assert abs(float(host(eta)) - eta_h) <= 1e-6 * eta_h
     finally:
         H.set_options(precision=0, refine_maxit=10, refine_tol=1e-12)
 
