@@ -742,19 +742,26 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         {
             Traced t(h, GPC_K_ADJ_DIAG_BLOCK, 3.0 * dbq * dbq * dbq, 8.0 * 8.0 * dbq * dbq);
             GPC_HIP(h, reduce_tril(s, (int)bq, Dbar, ldlb, Pd, sd, (int64_t)bb, Wd));
-            GemmArgs gp = gemm_args(bq, bq, bq, D, ldl, Wd, bq, Sw, bq);
-            gp.a_lower = 1;
-            GPC_HIP(h, gemm_f64(s, TILE_64, true, false, EPI_SYMLOW, false, gp, 1));
-            GemmArgs gt = gemm_args(bq, bq, bq, Sw, bq, Dq_inv, b, Tw, bq);
-            GPC_HIP(h, gemm_f64(s, TILE_64, false, false, EPI_STORE, false, gt, 1));
-            GemmArgs gm = gemm_args(bq, bq, bq, Dq_inv, b, Tw, bq, Mw, bq);
-            gm.C2 = Dbar;
-            gm.ldc2 = ldlb;
-            if (mixed) {
-                gm.Cf = Mf;
-                gm.ldcf = bq;
-            }
-            GPC_HIP(h, gemm_f64(s, TILE_64, true, false, EPI_PHI, false, gm, 1));
+            // S = sym(D^T W), T = S D^-1, M = D^-T T: three dependent bq^3
+            // products of only (bq/64)^2 output tiles each, so K is split in
+            // 64-row slices (partial sums in Pd, free again after reduce_tril)
+            // and a reduction applies each product's epilogue.  T is formed
+            // as its transpose D^-T S (S is symmetric), so that all three
+            // products read their A operand k-major.
+            const int sk = (int)std::max<int64_t>(1, (bq + 63) / 64);
+            auto part = [&](const double* A, int64_t lda, const double* B, int64_t ldbb, int alow) -> hipError_t {
+                GemmArgs g = gemm_args(bq, bq, bq, A, lda, B, ldbb, Pd, bq);
+                g.a_lower = alow;
+                g.kchunk = 64;
+                g.pstride = (int64_t)bb;
+                return gemm_f64(s, TILE_64, true, false, EPI_PARTIAL, false, g, sk);
+            };
+            GPC_HIP(h, part(D, ldl, Wd, bq, 1));
+            GPC_HIP(h, reduce_epi(s, (int)bq, Pd, sk, (int64_t)bb, 0, Sw, bq, nullptr, 0, nullptr, 0));
+            GPC_HIP(h, part(Dq_inv, b, Sw, bq, 0));
+            GPC_HIP(h, reduce_epi(s, (int)bq, Pd, sk, (int64_t)bb, 1, Tw, bq, nullptr, 0, nullptr, 0));
+            GPC_HIP(h, part(Dq_inv, b, Tw, bq, 0));
+            GPC_HIP(h, reduce_epi(s, (int)bq, Pd, sk, (int64_t)bb, 2, Mw, bq, mixed ? Mf : nullptr, bq, Dbar, ldlb));
         }
         if (j == 0) continue;
         // ---- updates of Bbar and Rbar, columns [c0, c0 + nc)

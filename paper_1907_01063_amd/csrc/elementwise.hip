@@ -71,7 +71,40 @@ __global__ void reduce_tril_kernel(int b, const double* D, int64_t ldd, const do
     W[e] = v;
 }
 
+// Element (r, c) of a b x b sum v = sum_z P[z][r][c] (P: b x b slices,
+// slice stride pstride) stored with the epilogue of mode: 0 C[r][c] = C[c][r]
+// = v for r >= c; 1 C[c][r] = v; 2 C[r][c] = v, Cf[r][c] = (float)v if Cf,
+// C2[r][c] = r > c ? v : r == c ? v / 2 : 0.
+__global__ void reduce_epi_kernel(int b, const double* P, int S, int64_t pstride, int mode, double* C, int64_t ldc,
+                                  float* Cf, int64_t ldcf, double* C2, int64_t ldc2)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= b * b) return;
+    const int r = e / b, c = e % b;
+    if (mode == 0 && r < c) return;
+    const double v = slice_sum(P + e, S, pstride);
+    if (mode == 0) {
+        C[(int64_t)r * ldc + c] = v;
+        C[(int64_t)c * ldc + r] = v;
+    } else if (mode == 1) {
+        C[(int64_t)c * ldc + r] = v;
+    } else {
+        C[(int64_t)r * ldc + c] = v;
+        if (Cf) Cf[(int64_t)r * ldcf + c] = (float)v;
+        C2[(int64_t)r * ldc2 + c] = r > c ? v : (r == c ? 0.5 * v : 0.0);
+    }
+}
+
 }  // namespace
+
+hipError_t reduce_epi(hipStream_t s, int b, const double* P, int S, int64_t pstride, int mode, double* C,
+                      int64_t ldc, float* Cf, int64_t ldcf, double* C2, int64_t ldc2)
+{
+    if (b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_epi_kernel, dim3((unsigned)((b * b + 255) / 256)), dim3(256), 0, s, b, P, S, pstride,
+                       mode, C, ldc, Cf, ldcf, C2, ldc2);
+    return hipGetLastError();
+}
 
 hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v)
 {

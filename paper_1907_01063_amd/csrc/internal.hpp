@@ -81,6 +81,11 @@ hipError_t zero_strict_upper(hipStream_t s, int64_t n, double* A, int64_t lda);
 hipError_t reduce_sub(hipStream_t s, int64_t M, int64_t N, const double* P, int S,
                       int64_t pstride, double* C, int64_t ldc);
 // W[m][n] = m >= n ? D[m][n] - sum_z P[z][m][n] : 0   (b x b, W leading dim b)
+// b x b split-K sums (slices of P, stride pstride, z increasing) stored with an
+// epilogue: mode 0 symmetric from the lower triangle (C[r][c] = C[c][r]),
+// 1 transposed (C[c][r]), 2 as EPI_PHI (C, optional FP32 copy Cf, C2 = phi).
+hipError_t reduce_epi(hipStream_t s, int b, const double* P, int S, int64_t pstride, int mode, double* C,
+                      int64_t ldc, float* Cf, int64_t ldcf, double* C2, int64_t ldc2);
 hipError_t reduce_tril(hipStream_t s, int b, const double* D, int64_t ldd, const double* P,
                        int S, int64_t pstride, double* W);
 
