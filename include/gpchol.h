@@ -64,7 +64,9 @@ typedef struct {
     int32_t mixed_fallback; /* GPC_MIXED factor: 1 (default) = keep a copy of A and, if the
                                FP32-updated Schur complement loses definiteness (info != 0),
                                factor again in FP64 from the copy (see gpc_get_fallback) */
-    int32_t reserved;      /* 0 */
+    int32_t test_flags;    /* 0; 1 = start every one-launch solve sweep (a single right-hand
+                              side) with its error flag raised: its waits return at once and
+                              its solution entries are NaN, which tests the failure path */
 } gpc_options;
 
 typedef struct gpc_handle gpc_handle;

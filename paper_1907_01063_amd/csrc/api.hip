@@ -402,6 +402,7 @@ gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
         return GPC_ERR_ARG;
     if (o->refine_maxit < 0 || !(o->refine_tol > 0.0)) return GPC_ERR_ARG;
     if (o->mixed_fallback != 0 && o->mixed_fallback != 1) return GPC_ERR_ARG;
+    if (o->test_flags != 0 && o->test_flags != 1) return GPC_ERR_ARG;
     h->opt = *o;
     return GPC_OK;
 }
@@ -854,7 +855,7 @@ gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const
     double* Y = Cpl + n_dinv;
     GPC_HIP(h, diag_block_inverses(s, n, b, L, ldl, Dinv, Cpl));
     GPC_HIP(h, trsm_couplings(s, trans, n, L, ldl, Dinv, b, Cpl));
-    GPC_HIP(h, trsm_blocked(s, trans, n, nrhs, L, ldl, Dinv, Cpl, b, B, ldb, Y, h->cus));
+    GPC_HIP(h, trsm_blocked(s, trans, n, nrhs, L, ldl, Dinv, Cpl, b, B, ldb, Y, h->cus, h->opt.test_flags));
     return GPC_OK;
 }
 
@@ -895,9 +896,9 @@ gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, 
         GPC_HIP(h, trsm_couplings(s, 0, n, L, ldl, Dinv, b, Cf));
         GPC_HIP(h, trsm_couplings(s, 1, n, L, ldl, Dinv, b, Cb));
         GPC_HIP(h, vec_copy(s, n, y, z));
-        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, z, 1, Y, h->cus));
+        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, z, 1, Y, h->cus, h->opt.test_flags));
         GPC_HIP(h, vec_copy(s, n, z, alpha));
-        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, alpha, 1, Y, h->cus));
+        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, alpha, 1, Y, h->cus, h->opt.test_flags));
     }
     GPC_HIP(h, logdet(s, n, L, ldl, logdet_out));
     GPC_HIP(h, gp_value(s, n, z, logdet_out, f_out));
@@ -967,8 +968,8 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
     while (it < maxit) {
         ++it;
         GPC_HIP(h, vec_copy(s, n, r, d));
-        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, d, 1, Y, h->cus));
-        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, d, 1, Y, h->cus));
+        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, d, 1, Y, h->cus, h->opt.test_flags));
+        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, d, 1, Y, h->cus, h->opt.test_flags));
         GPC_HIP(h, vec_axpy(s, n, d, x));
         if (it == 1)   // the row sums of |K| for eta come from the same pass over K
             GPC_HIP(h, symv_lower_abs(s, n, K, ldk, x, y, -1.0, r, rowabs, part));

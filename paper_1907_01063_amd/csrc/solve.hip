@@ -627,11 +627,12 @@ trsv_sweep1(int64_t n, int64_t nblk, const double* L, int64_t ldl, const double*
     }
 }
 
-// Zeroes the control words and fills the 2n hand-over entries with kPending.
-__global__ void sweep_init(uint32_t* ctrl, int64_t words, double* V, int64_t count)
+// Zeroes the control words (the error flag: fail) and fills the 2n
+// hand-over entries with kPending.
+__global__ void sweep_init(uint32_t* ctrl, int64_t words, double* V, int64_t count, int fail)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < words) ctrl[e] = 0u;
+    if (e < words) ctrl[e] = (e == kCtrlStride && fail) ? 1u : 0u;
     if (e < count) V[e] = __builtin_bit_cast(double, kPending);
 }
 
@@ -710,7 +711,7 @@ namespace {
 // one launch of at most four workgroups per compute unit.
 template <int BS>
 hipError_t sweep1(hipStream_t s, int trans, int64_t n, const double* L, int64_t ldl, const double* Dinv,
-                  const double* Cpl, double* B, int64_t ldb, double* Y, int cus)
+                  const double* Cpl, double* B, int64_t ldb, double* Y, int cus, int fail)
 {
     constexpr int P = BS * BS / 8192 + BS / 16;
     const int64_t nblk = (n + BS - 1) / BS;
@@ -719,7 +720,7 @@ hipError_t sweep1(hipStream_t s, int trans, int64_t n, const double* L, int64_t 
     uint32_t* ctrl = (uint32_t*)(Y + (int64_t)kRhsGroup * n + 2 * kSolveMax * kRhsGroup);
     const int64_t init = std::max<int64_t>(2 * n, ctrl_words(nblk));
     hipLaunchKernelGGL(sweep_init, dim3((unsigned)((init + 255) / 256)), dim3(256), 0, s, ctrl, ctrl_words(nblk), Yp,
-                       2 * n);
+                       2 * n, fail);
     const int64_t grid = std::min<int64_t>(nblk * P, 4 * (int64_t)std::max(cus, 1));
     if (!trans)
         hipLaunchKernelGGL((trsv_sweep1<BS, 0>), dim3((unsigned)grid), dim3(256), 0, s, n, nblk, L, ldl, Dinv, Cpl, B,
@@ -732,7 +733,7 @@ hipError_t sweep1(hipStream_t s, int trans, int64_t n, const double* L, int64_t 
 
 template <int BS>
 hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
-                 const double* Dinv, const double* Cpl, double* B, int64_t ldb, double* Y, int cus)
+                 const double* Dinv, const double* Cpl, double* B, int64_t ldb, double* Y, int cus, int fail)
 {
     constexpr int kLook = BS / 16;
     const int64_t nblk = (n + BS - 1) / BS;
@@ -742,7 +743,7 @@ hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double
         const int nr = (int)std::min<int64_t>(kRhsGroup, nrhs - c0);
         double* Bc = B + c0;
         if (nr == 1) {
-            const hipError_t e = sweep1<BS>(s, trans, n, L, ldl, Dinv, Cpl, Bc, ldb, Y, cus);
+            const hipError_t e = sweep1<BS>(s, trans, n, L, ldl, Dinv, Cpl, Bc, ldb, Y, cus, fail);
             if (e != hipSuccess) return e;
             continue;
         }
@@ -772,10 +773,11 @@ hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double
 }  // namespace
 
 hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
-                        const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb, double* Y, int cus)
+                        const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb, double* Y, int cus,
+                        int fail)
 {
-    if (b == 128) return sweep<128>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus);
-    if (b == 256) return sweep<256>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus);
+    if (b == 128) return sweep<128>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus, fail);
+    if (b == 256) return sweep<256>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus, fail);
     return hipErrorInvalidValue;
 }
 

@@ -181,6 +181,36 @@ def test_trsm_one_column_strided_repeatable(H, n):
         assert not np.isnan(outs[0]).any()
 
 
+def test_one_launch_sweep_failure_path(H):
+    """The one-launch sweep's failure path, forced from the host: with its
+    error flag raised before it starts, every wait returns at once and the
+    one-column solve completes with NaN entries; column-group solves are not
+    affected; clearing the flag restores normal results."""
+    from paper_1907_01063_amd.gpchol import GPC_ERR_ARG, GpcError
+    rng = np.random.default_rng(77)
+    n = 1500
+    _, L0 = W.spd_from_factor(rng, n)
+    B = rng.standard_normal((n, 3))
+    Lt = dev(L0)
+    with pytest.raises(GpcError) as ei:
+        H.set_options(test_flags=2)
+    assert ei.value.status == GPC_ERR_ARG
+    H.set_options(test_flags=1)
+    try:
+        for trans in (False, True):
+            z = dev(B[:, :1])
+            H.trsm(Lt, z, trans=trans)
+            assert np.isnan(host(z)).all()
+        Z3 = dev(B)
+        H.trsm(Lt, Z3)
+        assert relf(host(Z3), oracle.trsm(L0, B)) <= TOL
+    finally:
+        H.set_options(test_flags=0)
+    z = dev(B[:, :1])
+    H.trsm(Lt, z)
+    assert relf(host(z), oracle.trsm(L0, B[:, :1])) <= TOL
+
+
 def test_trsm_vector_and_logdet(H):
     case = W.c3(n=777)
     Lo, _ = oracle.potrf(case["A"])
