@@ -419,26 +419,39 @@ __device__ uint32_t next_ticket(uint32_t* ctrl)
     return t;
 }
 
-// Forward strip: rows [q BS + r SR, +SR) of block q.  BS/32 threads per row,
-// slot s covering columns s, s + BS/32, ... of each block p; the slot sums
-// run over p in increasing order and are combined in a fixed tree.
+// Forward strip: rows [q BS + r SR, +SR) of block q (SR = 8192/BS).  Thread
+// (row group g = tid/32, slot s = tid%32) covers rows g, g+8, ... of the strip
+// and columns s, s+32, ... of each block p, so that a wave load reads two
+// 256-byte row segments; each row's 32 slot sums run over p in increasing
+// order and are combined in a fixed tree.
 template <int BS>
 __device__ void fwd_strip(int64_t n, int64_t q, int r, const double* L, int64_t ldl, const double* B, int64_t ldb,
                           const double* Zs, double* Yp, uint32_t* ctrl, double* zs)
 {
-    constexpr int TPR = BS / 32, SR = 256 / TPR, K = BS / 16;
-    const int slot = threadIdx.x % TPR;
-    const int64_t row = q * BS + (int64_t)r * SR + threadIdx.x / TPR;
-    const bool live = row < n;
-    // y_row is only overwritten (by the solution) after this strip's y' is
-    // read, so it is loaded first, off the path of the last block
-    const double yv = (slot == 0 && live) ? ld_dev(B + row * ldb) : 0.0;
-    double acc = 0.0;
-    for (int64_t p = 0; p + 2 <= q; ++p) {
-        double v[32];
-        const double* lr = L + (live ? row : 0) * ldl + p * BS + slot;
+    constexpr int SR = 8192 / BS, RPT = SR / 8, CPT = BS / 32, K = BS / 16;
+    static_assert(RPT * CPT == 32, "32 values of L per thread and block");
+    const int slot = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int64_t row0 = q * BS + (int64_t)r * SR + g;
+    // y is only overwritten (by the solution) after this strip's y' is read,
+    // so it is loaded first, off the path of the last block
+    double yv[RPT];
 #pragma unroll
-        for (int k = 0; k < 32; ++k) v[k] = live ? lr[TPR * k] : 0.0;
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t row = row0 + 8 * i;
+        yv[i] = (slot == 0 && row < n) ? ld_dev(B + row * ldb) : 0.0;
+    }
+    double acc[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) acc[i] = 0.0;
+    for (int64_t p = 0; p + 2 <= q; ++p) {
+        double v[RPT][CPT];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int64_t row = row0 + 8 * i;
+            const double* lr = L + (row < n ? row : 0) * ldl + p * BS + slot;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) v[i][c] = row < n ? lr[32 * c] : 0.0;
+        }
         if (p + 2 < q) {
             wait_count(zdone(ctrl, p), K, ctrl + kCtrlStride);
             if ((int)threadIdx.x < BS) zs[threadIdx.x] = ld_dev(Zs + p * BS + threadIdx.x);
@@ -447,15 +460,21 @@ __device__ void fwd_strip(int64_t n, int64_t q, int r, const double* L, int64_t 
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 32; ++k) acc += v[k] * zs[slot + TPR * k];
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) acc[i] += v[i][c] * zs[slot + 32 * c];
         __syncthreads();
     }
 #pragma unroll
-    for (int w = 1; w < TPR; w <<= 1) {
-        const double o = __shfl_xor(acc, w, 64);
-        acc = (slot & w) ? o + acc : acc + o;
+    for (int i = 0; i < RPT; ++i) {
+#pragma unroll
+        for (int w = 1; w < 32; w <<= 1) {
+            const double o = __shfl_xor(acc[i], w, 64);
+            acc[i] = (slot & w) ? o + acc[i] : acc[i] + o;
+        }
+        const int64_t row = row0 + 8 * i;
+        if (slot == 0 && row < n) st_dev(Yp + row, yv[i] - acc[i]);
     }
-    if (slot == 0 && live) st_dev(Yp + row, yv - acc);
 }
 
 // Forward chain item c of block q: rows [16c, 16c+16) of
