@@ -154,6 +154,7 @@ reduce_parts(int64_t ntiles, int m, const double* part, const double* scale, dou
     __shared__ double red[256];
     const int q = blockIdx.x;
     double s = 0.0;
+#pragma unroll 8   // eight loads in flight; the additions keep their order
     for (int64_t t = threadIdx.x; t < ntiles; t += 256) s += part[t * m + q];
     s = block_sum(s, red);
     if (threadIdx.x == 0) grad[q] = (scale ? *scale : 1.0) * s;
@@ -164,6 +165,7 @@ gp_value_kernel(int64_t n, const double* z, const double* logdet, double* f)
 {
     __shared__ double red[256];
     double s = 0.0;
+#pragma unroll 8   // eight loads in flight; the additions keep their order
     for (int64_t i = threadIdx.x; i < n; i += 256) s += z[i] * z[i];
     s = block_sum(s, red);
     if (threadIdx.x == 0) *f = -0.5 * s - 0.5 * (*logdet);
@@ -273,6 +275,7 @@ eta_kernel(int64_t n, const double* r, const double* x, const double* y, const d
 {
     __shared__ double red[4][256];
     double mr = 0.0, mx = 0.0, my = 0.0, mk = 0.0;
+#pragma unroll 8   // eight loads of each vector in flight
     for (int64_t i = threadIdx.x; i < n; i += 256) {
         mr = fmax(mr, fabs(r[i]));
         mx = fmax(mx, fabs(x[i]));

@@ -272,7 +272,17 @@ __global__ void __launch_bounds__(256) logdet_kernel(int64_t n, const double* L,
 {
     __shared__ double red[256];
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s += log(L[i * ldl + i]);
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * 256) {   // eight loads in flight, sums in order
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = i0 + 256 * k;
+            v[k] = i < n ? L[i * ldl + i] : 1.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (i0 + 256 * k < n) s += log(v[k]);
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
