@@ -7,7 +7,9 @@ n = 16384 (the headline Matern-3/2 workload), where the oracle is too slow:
   depends only on the leading block of A), and properties that hold at any
   size: sampled rows of L L^T - A, the exact closed form Abar(Lbar = L) = I/2,
   and the GP identity K M = y alpha^T - I for M = Abar + Abar^T (diagonal
-  counted once) with the GP adjoint seed, on sampled columns, in NumPy FP64.
+  counted once) with the GP adjoint seed, on sampled columns, in NumPy FP64;
+  the one-launch triangular sweeps: backward error, bit-for-bit repetition,
+  and agreement with the column-group sweeps on the same right-hand side.
 n = 30000 (the 8-D SE-ARD GP): the hyper-gradient against central finite
   differences of the log-likelihood value.
 """
@@ -85,6 +87,32 @@ def test_n16384_adjoint_identity(H, c3):
     say(f"  Abar(L) = I/2: diag err {e_diag:.2e}, off-diag max {e_off:.2e}")
     assert e_diag <= 1e-11 and e_off <= 1e-11
     assert torch.count_nonzero(torch.triu(Ab, 1)).item() == 0
+
+
+def test_n16384_one_column_sweeps(H, c3):
+    At = dev(c3["A"])
+    assert int(host(H.factor(At))) == 0
+    Lt = torch.tril(At)
+    y = dev(c3["y"])
+    for trans in (False, True):
+        z = y.clone()
+        H.trsm(At, z, trans=trans)
+        z2 = y.clone()
+        H.trsm(At, z2, trans=trans)
+        Y3 = y.unsqueeze(1).repeat(1, 3).contiguous()   # three columns: the column-group sweeps
+        H.trsm(At, Y3, trans=trans)
+        M = Lt.T if trans else Lt
+        r = M @ z - y
+        # normwise backward error of the solve with M (Rigal-Gaches); a
+        # backward-stable triangular solve keeps it below gamma_n ~ 2e-12
+        nrmM = M.abs().sum(dim=1).max().item()
+        eta = r.abs().max().item() / (nrmM * z.abs().max().item() + y.abs().max().item())
+        dgrp = ((Y3[:, 0] - z).abs().max() / z.abs().max()).item()
+        say(f"  trans={trans}: eta {eta:.2e}, vs column-group sweep {dgrp:.2e}")
+        assert not torch.isnan(z).any()
+        assert torch.equal(z, z2)
+        assert eta <= 1e-14
+        assert dgrp <= 1e-12
 
 
 def test_n16384_gp_adjoint_identity(H, c3):
