@@ -36,20 +36,79 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample: int):
-    """The oracle's factor + adjoint on a same-density sample of the workload."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_time(case) -> float:
+    """Seconds of the oracle's factor + adjoint of one case."""
     import oracle
-    import workloads as W
-    case = W.c3(n=n_sample)
     t0 = time.perf_counter()
     L, _ = oracle.potrf(case["A"])
     oracle.potrf_adjoint(L, case["Lbar"])
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(n_sample: int, per_config: bool):
+    """The oracle's factor + adjoint on a same-density sample of the workload
+    (the headline line), and, per workload, the oracle's times with the
+    paper's repetition protocol where they fit in a bounded run."""
+    import statistics
+    import oracle
+    import workloads as W
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_threads(cores)
+    threads = oracle.threads()
+    case = W.c3(n=n_sample)
+    dt = oracle_time(case)
     F = W.flops_factor(n_sample) + W.flops_adjoint(n_sample)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return {"value": round(F / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"factor+adjoint of the same-density Matern-3/2 matrix at n={n_sample}, 1 run, "
-                      f"{dt:.1f} s (GFLOP/s with the same flop count)"}
+    out = {"value": round(F / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"factor+adjoint of the same-density Matern-3/2 matrix at n={n_sample}, 1 run, "
+                     f"{dt:.1f} s (GFLOP/s with the same flop count)",
+           "cpu_model": cpu_model(), "host_cpus_available": cores, "omp_threads": threads}
+    del case
+    if not per_config:
+        return out
+    pc = {}
+    c1 = W.c1()
+    F1 = W.flops_factor(256) + W.flops_adjoint(256)
+    for t in (1, cores):
+        oracle.set_threads(t)
+        ts = sorted(oracle_time(c1) for _ in range(9))
+        pc[f"se1d-n256 threads={t}"] = {"median_s": statistics.median(ts), "min_s": ts[0],
+                                        "gflops_median": round(F1 / statistics.median(ts) / 1e9, 3),
+                                        "protocol": "median of 9"}
+        log(f"oracle se1d-n256 threads={t}: median {statistics.median(ts) * 1e3:.2f} ms")
+    oracle.set_threads(cores)
+    c2 = W.c2()
+    F2 = W.flops_factor(4096) + W.flops_adjoint(4096)
+    ts = sorted(oracle_time(c2) for _ in range(3))
+    pc[f"se4d-n4096 threads={cores}"] = {"median_s": statistics.median(ts), "min_s": ts[0],
+                                         "gflops_median": round(F2 / statistics.median(ts) / 1e9, 3),
+                                         "protocol": "median of 3"}
+    log(f"oracle se4d-n4096: median {statistics.median(ts):.2f} s")
+    del c2
+    bc = W.c4()
+    t0 = time.perf_counter()
+    Fb = 0.0
+    for nb, off in zip(bc["n"], bc["off"]):
+        nb = int(nb)
+        A = bc["base"][off:off + nb * nb].reshape(nb, nb)
+        Lb = bc["Lbar"][off:off + nb * nb].reshape(nb, nb)
+        L, _ = oracle.potrf(A)
+        oracle.potrf_adjoint(L, Lb)
+        Fb += W.flops_factor(nb) + W.flops_adjoint(nb)
+    tb = time.perf_counter() - t0
+    pc[f"se3d-batch512 threads={cores}"] = {"s": tb, "gflops": round(Fb / tb / 1e9, 3), "protocol": "1 run"}
+    log(f"oracle se3d-batch512: {tb:.2f} s")
+    out["per_config"] = pc
+    return out
 
 
 def measured_traffic(kernel: str):
@@ -72,15 +131,24 @@ def measured_traffic(kernel: str):
     return round(rec["traffic_bytes_per_launch"])
 
 
-def timed(fn, steps, warmup):
+PROGRESS = False   # --progress: one line per step (each step then waits for the GPU)
+
+
+def timed(fn, steps, warmup, what=""):
     import torch
-    for _ in range(warmup):
+    for i in range(warmup):
         fn()
+        if PROGRESS:
+            torch.cuda.synchronize()
+            log(f"{what} warmup step {i + 1}/{warmup} done")
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(steps):
+    for i in range(steps):
         fn()
+        if PROGRESS:
+            torch.cuda.synchronize()
+            log(f"{what} step {i + 1}/{steps} done")
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
@@ -95,8 +163,13 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--lookahead", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=8192)
-    ap.add_argument("--gp-evals", type=int, default=3)
+    ap.add_argument("--gp-evals", type=int, default=10,
+                    help="GP gradient evaluations timed per form (of the workload's 100 jittered thetas)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-configs", action="store_true",
+                    help="skip the oracle's per-workload timings (the cpu_baseline sample only)")
+    ap.add_argument("--progress", action="store_true",
+                    help="log every step after waiting for it (for profiler runs; timing is then not meaningful)")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--serial-classes", action="store_true",
                     help="also trace one step with lookahead off (per-class kernel times, each kernel alone)")
@@ -105,6 +178,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
+    global PROGRESS
+    PROGRESS = args.progress
 
     import numpy as np
     import torch
@@ -138,16 +213,19 @@ def main():
         Lb.copy_(Lb0)
         H.adjoint(L, Lb)
 
-    ms = timed(step64, args.steps, args.warmup)
+    log(f"fp64: {args.warmup} warmup + {args.steps} timed steps")
+    ms = timed(step64, args.steps, args.warmup, "fp64")
+    H.check()   # raises if a one-launch solve sweep ran out of time
     tr_timed = None
     if not args.no_trace:
         # the same number of steps again, same schedule, with the library's
         # launch trace on: every kernel launch bracketed by HIP events on the
         # stream it runs on (the events cost about 4 % of a step, so the
         # step time above is taken without them)
+        log("fp64: traced steps")
         H.trace_reset()
         H.trace_enable(True)
-        timed(step64, args.steps, 0)
+        timed(step64, args.steps, 0, "fp64 traced")
         tr_timed = H.trace_read()
         H.trace_enable(False)
     if int(info.item()) != 0:
@@ -224,12 +302,14 @@ def main():
             Lbm.copy_(Lb0)
             Hm.adjoint(Lm, Lbm)
 
-        msm = timed(stepmix, args.steps, args.warmup)
+        log(f"mixed: {args.warmup} warmup + {args.steps} timed steps")
+        msm = timed(stepmix, args.steps, args.warmup, "mixed")
+        Hm.check()
         trm = None
         if not args.no_trace:
             Hm.trace_reset()
             Hm.trace_enable(True)
-            timed(stepmix, args.steps, 0)
+            timed(stepmix, args.steps, 0, "mixed traced")
             trm = {k: round(v[1] / args.steps, 3) for k, v in Hm.trace_read().items() if v[0]}
             Hm.trace_enable(False)
         cpm = timed(lambda: Lm.copy_(A0), 2, 0)
@@ -269,7 +349,7 @@ def main():
             lw.copy_(lbar0)
             Hb.factor_adjoint_batched(bc["n"], bc["off"], bw, lw, binfo)
 
-        msb = timed(stepb, args.steps, args.warmup)
+        msb = timed(stepb, args.steps, args.warmup, "batched")
         Fb = float(sum(W.flops_factor(int(k)) + W.flops_adjoint(int(k)) for k in bc["n"]))
         Hb.trace_enable(True)
         Hb.trace_reset()
@@ -291,7 +371,7 @@ def main():
             lw.copy_(lbar0)
             Hbm.factor_adjoint_batched(bc["n"], bc["off"], bw, lw, binfo)
 
-        msbm = timed(stepbm, args.steps, args.warmup)
+        msbm = timed(stepbm, args.steps, args.warmup, "batched mixed")
         Hbm.trace_enable(True)
         Hbm.trace_reset()
         stepbm()
@@ -323,9 +403,16 @@ def main():
                 f = gp_mll(X, Y, th, precision=prec, handle=Hg, check=False)
                 f.backward()
                 return f, th.grad
-            msg = timed(ev, args.gp_evals, 1)
+            log(f"gp {name}: 1 warmup + {args.gp_evals} timed evaluations")
+            msg = timed(ev, args.gp_evals, 1, f"gp {name}")
+            Hg.check()
             Fg = W.flops_factor(ngp) + W.flops_adjoint(ngp)
-            gp[name] = {"ms_per_eval": round(msg, 2), "gflops_factor_adjoint": round(Fg / (msg * 1e-3) / 1e9, 2)}
+            ne = thetas.shape[0]
+            gp[name] = {"ms_per_eval": round(msg, 2), "gflops_factor_adjoint": round(Fg / (msg * 1e-3) / 1e9, 2),
+                        f"s_for_{ne}_evals": round(msg * ne / 1e3, 2),
+                        "timing": (f"{args.gp_evals} evaluations timed (jittered thetas 1..{args.gp_evals} of {ne}, "
+                                   f"after 1 warmup); s_for_{ne}_evals = ms_per_eval x {ne}"
+                                   + ("" if args.gp_evals >= ne else ", extrapolated"))}
             log(f"gp {name}: {msg:.1f} ms per value+gradient evaluation")
         th0 = thetas[0].clone().requires_grad_(True)
         f64v = gp_mll(X, Y, th0, precision=GPC_FP64, handle=Hg)
@@ -345,7 +432,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) at n={args.cpu_sample}")
-        cpu = cpu_baseline(args.cpu_sample)
+        cpu = cpu_baseline(args.cpu_sample, not args.no_oracle_configs)
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",

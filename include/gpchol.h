@@ -6,9 +6,10 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * - Matrices are row-major FP64 with a leading dimension `ld >= max(1, n)`:
- *   element (i, j) of X is X[i * ld + j].  (Row-major lower is the same memory
- *   as column-major upper.)
+ * - Matrices are row-major FP64 with a leading dimension
+ *   max(1, n) <= ld <= 2^20: element (i, j) of X is X[i * ld + j].  (Row-major
+ *   lower is the same memory as column-major upper.)  A leading dimension out
+ *   of that range is GPC_ERR_ARG, found before anything is enqueued.
  * - Symmetric inputs are given by their lower triangle including the
  *   diagonal; the strict upper triangle of an input is never read.
  *   Triangular outputs are lower; their strict upper triangle is written as 0.
@@ -36,12 +37,17 @@ extern "C" {
 
 typedef enum {
     GPC_OK = 0,
-    GPC_ERR_ARG = 1,        /* invalid argument: n < 0, ld < max(1,n), NULL pointer, bad enum */
+    GPC_ERR_ARG = 1,        /* invalid argument: n < 0, ld outside [max(1,n), 2^20], NULL pointer,
+                               bad enum, an output overlapping an input */
     GPC_ERR_NO_DEVICE = 2,  /* no HIP device is visible */
     GPC_ERR_ARCH = 3,       /* the current device is not gfx950 */
     GPC_ERR_HIP = 4,        /* a HIP runtime call failed; gpc_last_error() has the message */
     GPC_ERR_REFINE = 5,     /* iterative refinement did not reach its tolerance */
-    GPC_ERR_ALLOC = 6       /* workspace allocation failed */
+    GPC_ERR_ALLOC = 6,      /* workspace allocation failed */
+    GPC_ERR_SWEEP = 7,      /* a one-launch solve sweep ran out of time; its results are NaN
+                               (reported by gpc_check and gpc_solve_refined) */
+    GPC_ERR_CAPTURE = 8     /* the stream is capturing a graph and the call would need work
+                               that cannot be captured (see the batched entry points) */
 } gpc_status;
 
 typedef enum {
@@ -61,9 +67,11 @@ typedef struct {
     int32_t lookahead;     /* 1 = overlap the next diagonal step with the trailing update */
     int32_t refine_maxit;  /* maximum refinement iterations of gpc_solve_refined (default 10) */
     double  refine_tol;    /* stop when the normwise backward error eta_inf <= refine_tol (default 1e-12) */
-    int32_t mixed_fallback; /* GPC_MIXED factor: 1 (default) = keep a copy of A and, if the
-                               FP32-updated Schur complement loses definiteness (info != 0),
-                               factor again in FP64 from the copy (see gpc_get_fallback) */
+    int32_t mixed_fallback; /* GPC_MIXED factor: 0 (default) = none: a lost pivot of the
+                               FP32-updated Schur complement is reported in info, and a caller
+                               that still holds A factors it again in FP64; 1 = the library
+                               keeps a copy of A and does that itself (see gpc_factor and
+                               gpc_get_fallback) */
     int32_t test_flags;    /* 0; 1 = start every one-launch solve sweep (a single right-hand
                               side) with its error flag raised: its waits return at once and
                               its solution entries are NaN, which tests the failure path */
@@ -80,8 +88,18 @@ gpc_status gpc_create(gpc_handle** h, void* hip_stream);
 /* Wait for the handle's stream, free its workspace and the handle. */
 gpc_status gpc_destroy(gpc_handle* h);
 
-/* Rebind the handle to another stream of the same device. */
+/* Rebind the handle to another stream of the same device.  The new stream
+ * first waits (a HIP event, no host wait) for all work enqueued on the old
+ * one, because every call shares the handle's workspace; when either stream
+ * is capturing a graph there is no such wait, and ordering the captured work
+ * against the handle's other work is up to the caller. */
 gpc_status gpc_set_stream(gpc_handle* h, void* hip_stream);
+
+/* Wait for the handle's stream and report whether a one-launch solve sweep
+ * (gpc_trsm with one right-hand side, gpc_gp_value, gpc_solve_refined) has
+ * run out of time since the last check: GPC_ERR_SWEEP (the record is then
+ * cleared; the results of that sweep are NaN) or GPC_OK. */
+gpc_status gpc_check(gpc_handle* h);
 
 /* Replace the handle's options (copied).  GPC_ERR_ARG on NULL, an unknown
  * precision, block not in {0, 32, 64, 128, 256, 512}, refine_maxit < 0 or
@@ -99,7 +117,8 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* opt);
  * buffer (n x n doubles, grow-only), the call waits for the stream once to
  * read info, and on a failed pivot restores A and factors it again in FP64;
  * info then reports the FP64 result (so a matrix that is not SPD in FP64
- * still gets its failing column).  Such a call cannot be graph-captured. */
+ * still gets its failing column).  Such a call returns GPC_ERR_CAPTURE if
+ * the stream is capturing a graph. */
 gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info_dev);
 
 /* *fell_back = 1 if the last gpc_factor on this handle was a GPC_MIXED call
@@ -112,21 +131,25 @@ gpc_status gpc_get_fallback(const gpc_handle* h, int32_t* fell_back);
  * the lower triangle of L.  In place: the lower triangle of Lbar becomes Abar,
  * the gradient with respect to the independent lower-triangle entries a_ij
  * (i >= j) of the symmetric A (a perturbation of a_ij, i > j, moves both A_ij
- * and A_ji); its strict upper triangle becomes 0.  L and Lbar must not overlap. */
+ * and A_ji); its strict upper triangle becomes 0.  L and Lbar must not overlap
+ * (GPC_ERR_ARG if their byte ranges intersect). */
 gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl,
                        double* Lbar, int64_t ldlb);
 
 /* Triangular solve with the factor (section 3.2, A x = b with A triangular):
  * B <- L^-1 B (trans = GPC_NOTRANS) or B <- L^-T B (GPC_TRANS).
- * B is n x nrhs row-major with leading dimension ldb >= max(1, nrhs).
- * A single column is solved in one launch whose workgroups wait on each
- * other with bounded waits; were a wait ever to run out, the entries it
- * guards would be NaN (the call itself cannot report it). */
+ * B is n x nrhs row-major with leading dimension ldb >= max(1, nrhs); B must
+ * not overlap L.  A single column is solved in one launch whose workgroups
+ * wait on each other; every wait is bounded in time (100 ms): were one ever
+ * to run out, the entries it guards are NaN and gpc_check (or the next
+ * gpc_solve_refined) returns GPC_ERR_SWEEP. */
 gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs,
                     const double* L, int64_t ldl, double* B, int64_t ldb);
 
-/* log|A| = 2 * sum_i log L_ii, accumulated in FP64 in a fixed order
- * (independent of launch shape).  out_dev: one device double. */
+/* log|A| = 2 * sum_i log L_ii (section 1: the GP log-density needs the
+ * determinant of the covariance, taken here through its factor), accumulated
+ * in FP64 in a fixed order (independent of launch shape).  out_dev: one
+ * device double. */
 gpc_status gpc_logdet(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* out_dev);
 
 /* Iterative refinement (mixed precision): solve K x = y in FP64 with a
@@ -137,7 +160,9 @@ gpc_status gpc_logdet(gpc_handle* h, int64_t n, const double* L, int64_t ldl, do
  * the handle's refine_tol, or refine_maxit iterations have run.  y, x: device
  * n-vectors; iters_dev (int32) and eta_dev (double): device scalars.  Waits
  * for the stream once per iteration to read eta.  Returns GPC_ERR_REFINE if
- * the tolerance was not reached (x, iters and eta are still written). */
+ * the tolerance was not reached (x, iters and eta are still written), and
+ * GPC_ERR_SWEEP if one of its sweeps ran out of time (x is then not a
+ * solution).  x must not overlap K, L or y. */
 gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t ldk, const double* L,
                              int64_t ldl, const double* y, double* x, int32_t* iters_dev, double* eta_dev);
 
@@ -177,9 +202,15 @@ gpc_status gpc_gp_hypergrad_se(gpc_handle* h, int64_t n, int32_t d, const double
  * blocked algorithms as gpc_factor / gpc_adjoint, inner block chosen per size
  * bucket by gpc_autotune_batched, default 64).  The launch is captured once
  * into a HIP graph per distinct (sizes, offsets, pointers) and replayed on
- * later calls; if the handle's stream is itself being captured, the launch is
- * recorded into the caller's graph instead.  Results are bitwise independent
- * of queue order.  info_dev: nb device int32 (0 or first failing column + 1).
+ * later calls.  If the handle's stream is itself being captured, the launch
+ * is recorded into the caller's graph instead, provided the same call (same
+ * sizes, offsets and pointers) has been made once outside the capture, which
+ * prepares its plan; otherwise the call returns GPC_ERR_CAPTURE and enqueues
+ * nothing.  The buffers of a plan recorded into a caller's graph stay
+ * allocated until gpc_destroy (the graph must not be launched after that).
+ * Concurrent launches of one handle's plan (graph replays on two streams)
+ * share its queue counter and race.  Results are bitwise independent of
+ * queue order.  info_dev: nb device int32 (0 or first failing column + 1).
  * The handle's precision applies: GPC_MIXED runs the trailing update and the
  * B-bar / R-bar products in FP32 on MFMA (operands rounded from FP64 on load,
  * FP32 accumulation subtracted from FP64 storage); diagonal blocks, panels and
@@ -199,8 +230,8 @@ gpc_status gpc_factor_adjoint_batched(gpc_handle* h, int32_t nb, const int32_t* 
  * with inner blocks 32 and 64 (median of 3) and keep the faster.  If
  * cache_path is not NULL the choices are written there; handles read the file
  * named by the environment variable GPC_TUNE_CACHE at creation.  Waits for
- * the stream.  gpc_get_tuning returns the 5 bucket blocks and whether they
- * come from tuning. */
+ * the stream (GPC_ERR_CAPTURE if it is capturing).  gpc_get_tuning returns
+ * the 5 bucket blocks and whether they come from tuning. */
 gpc_status gpc_autotune_batched(gpc_handle* h, const char* cache_path);
 gpc_status gpc_get_tuning(const gpc_handle* h, int32_t* blocks_out, int32_t* tuned);
 

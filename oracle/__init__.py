@@ -60,11 +60,25 @@ def _load():
                                        ctypes.c_double, _dp, _i64]
         lib.orc_gp_lbar.restype = None
         lib.orc_gp_lbar.argtypes = [_i64, _dp, _i64, _dp, _dp, _dp, _i64]
+        lib.orc_max_threads.restype = ctypes.c_int
+        lib.orc_max_threads.argtypes = []
+        lib.orc_set_threads.restype = None
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_gp_hypergrad_se.restype = None
         lib.orc_gp_hypergrad_se.argtypes = [_i64, _i64, _dp, ctypes.c_double, _dp,
                                             _dp, _i64, _dp]
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use (OpenMP)."""
+    return int(_load().orc_max_threads())
+
+
+def set_threads(t: int) -> None:
+    """Set the oracle's thread count (its results do not depend on it)."""
+    _load().orc_set_threads(int(t))
 
 
 def _c(a: np.ndarray) -> np.ndarray:

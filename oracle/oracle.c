@@ -20,11 +20,16 @@
  * the thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define AT(X, ld, i, j) ((X)[(int64_t)(i) * (ld) + (j)])
+
+/* Thread count of the parallel loops (for timing; results do not depend on it). */
+int orc_max_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int t) { if (t > 0) omp_set_num_threads(t); }
 
 /* Rows per fixed chunk of the column reductions in the adjoint. */
 #define ORC_CHUNK 64

@@ -34,6 +34,7 @@ struct BatchPlan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double flops = 0.0;
+    bool pinned = false;   // recorded into a caller's graph: its buffers must outlive that graph
 };
 
 struct gpc_handle {
@@ -52,6 +53,9 @@ struct gpc_handle {
     double* acopy = nullptr;             // copy of A for the mixed factor's FP64 fallback
     size_t acopy_bytes = 0;
     int32_t fell_back = 0;
+    uint32_t* status_dev = nullptr;      // device words: [0] one-launch sweep failure record
+    std::vector<BatchPlan*> retired;     // plans a caller's graph may still use (freed at destroy)
+    hipEvent_t rebind_ev = nullptr;      // orders a new stream after the old one
     char err[256] = {0};
     bool trace = false;
     std::vector<TraceRec> recs;        // launches recorded since the last reset
@@ -145,6 +149,17 @@ void free_plan(BatchPlan* p)
     delete p;
 }
 
+// Drop the handle's current plan: freed now, or at gpc_destroy if a caller's
+// graph may still launch with its buffers.
+void retire_plan(gpc_handle* h)
+{
+    BatchPlan* p = h->plan;
+    h->plan = nullptr;
+    if (!p) return;
+    if (p->pinned) h->retired.push_back(p);
+    else free_plan(p);
+}
+
 int bucket_of(int32_t n)
 {
     for (int b = 0; b < kTuneBuckets; ++b)
@@ -195,7 +210,20 @@ int factor_block_of(const gpc_handle* h, int64_t n, bool mixed)
     return !mixed && n >= 8192 ? 2 * kDefaultBlock : kDefaultBlock;
 }
 
-bool ld_ok(int64_t n, int64_t ld) { return ld >= std::max<int64_t>(1, n); }
+// Leading dimensions: at least max(1, n) and at most 2^20 elements (the MFMA
+// tiles address 128 rows of an operand with 32-bit byte offsets).
+constexpr int64_t kMaxLd = int64_t(1) << 20;
+bool ld_ok(int64_t n, int64_t ld) { return ld >= std::max<int64_t>(1, n) && ld <= kMaxLd; }
+
+// Byte ranges of two row-major blocks (rows x cols, leading dimension ld)
+// intersect.  Empty blocks intersect nothing.
+bool overlap(const void* a, int64_t ra, int64_t ca, int64_t lda, const void* b, int64_t rb, int64_t cb, int64_t ldb)
+{
+    if (!a || !b || ra <= 0 || ca <= 0 || rb <= 0 || cb <= 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, a1 = a0 + sizeof(double) * (size_t)((ra - 1) * lda + ca);
+    const uintptr_t b0 = (uintptr_t)b, b1 = b0 + sizeof(double) * (size_t)((rb - 1) * ldb + cb);
+    return a0 < b1 && b0 < a1;
+}
 
 // Split-K plan: the split count s (at most max_splits, at least 256 k-values
 // per split, chunk a multiple of 32, the largest BK) that minimises the
@@ -301,6 +329,8 @@ const char* gpc_status_string(gpc_status s)
     case GPC_ERR_HIP: return "HIP runtime error";
     case GPC_ERR_REFINE: return "iterative refinement did not converge";
     case GPC_ERR_ALLOC: return "workspace allocation failed";
+    case GPC_ERR_SWEEP: return "a one-launch solve sweep ran out of time (its results are NaN)";
+    case GPC_ERR_CAPTURE: return "the call cannot be recorded into the stream's graph capture as prepared";
     }
     return "unknown status";
 }
@@ -327,8 +357,14 @@ gpc_status gpc_create(gpc_handle** out, void* stream)
     h->opt.lookahead = 1;
     h->opt.refine_maxit = 10;
     h->opt.refine_tol = 1e-12;
-    h->opt.mixed_fallback = 1;
+    h->opt.mixed_fallback = 0;
     h->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (hipMalloc((void**)&h->status_dev, 256) != hipSuccess || hipMemset(h->status_dev, 0, 256) != hipSuccess ||
+        hipEventCreateWithFlags(&h->rebind_ev, hipEventDisableTiming) != hipSuccess) {
+        if (h->status_dev) hipFree(h->status_dev);
+        delete h;
+        return GPC_ERR_HIP;
+    }
     load_tune_cache(h, getenv("GPC_TUNE_CACHE"));
     *out = h;
     return GPC_OK;
@@ -343,6 +379,9 @@ gpc_status gpc_destroy(gpc_handle* h)
     if (h->acopy && hipFree(h->acopy) != hipSuccess) st = GPC_ERR_HIP;
     for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
     free_plan(h->plan);
+    for (BatchPlan* p : h->retired) free_plan(p);
+    if (h->status_dev && hipFree(h->status_dev) != hipSuccess) st = GPC_ERR_HIP;
+    if (h->rebind_ev) hipEventDestroy(h->rebind_ev);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->side) hipStreamDestroy(h->side);
     for (hipEvent_t e : h->sync_ev) hipEventDestroy(e);
@@ -389,8 +428,33 @@ gpc_status gpc_trace_read(gpc_handle* h, int32_t kclass, int64_t* launches, doub
 gpc_status gpc_set_stream(gpc_handle* h, void* stream)
 {
     if (!h) return GPC_ERR_ARG;
-    h->stream = (hipStream_t)stream;
+    hipStream_t ns = (hipStream_t)stream;
+    if (ns == h->stream) return GPC_OK;
+    // the handle's workspace may still be in use by work queued on the old
+    // stream: the new stream waits for everything enqueued there so far.
+    // Not while either stream captures a graph (an event from outside a
+    // capture cannot be waited on inside it): a captured graph runs when
+    // its caller launches it, ordered by the caller.
+    hipStreamCaptureStatus c0 = hipStreamCaptureStatusNone, c1 = hipStreamCaptureStatusNone;
+    GPC_HIP(h, hipStreamIsCapturing(h->stream, &c0));
+    GPC_HIP(h, hipStreamIsCapturing(ns, &c1));
+    if (c0 == hipStreamCaptureStatusNone && c1 == hipStreamCaptureStatusNone) {
+        GPC_HIP(h, hipEventRecord(h->rebind_ev, h->stream));
+        GPC_HIP(h, hipStreamWaitEvent(ns, h->rebind_ev, 0));
+    }
+    h->stream = ns;
     return GPC_OK;
+}
+
+gpc_status gpc_check(gpc_handle* h)
+{
+    if (!h) return GPC_ERR_ARG;
+    uint32_t rec = 0;
+    GPC_HIP(h, hipMemcpyAsync(&rec, h->status_dev, sizeof(rec), hipMemcpyDeviceToHost, h->stream));
+    GPC_HIP(h, hipStreamSynchronize(h->stream));
+    if (rec == 0) return GPC_OK;
+    GPC_HIP(h, fill_i32(h->stream, (int32_t*)h->status_dev, 0));
+    return GPC_ERR_SWEEP;
 }
 
 gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
@@ -570,6 +634,9 @@ gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t*
     const bool mixed = h->opt.precision == GPC_MIXED;
     if (!mixed || !h->opt.mixed_fallback || n == 0) return factor_impl(h, n, A, lda, info, mixed);
     hipStream_t s = h->stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    GPC_HIP(h, hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return GPC_ERR_CAPTURE;   // it copies, allocates and waits
     const size_t bytes = sizeof(double) * (size_t)n * (size_t)n;
     if (bytes > h->acopy_bytes) {
         if (h->acopy) {
@@ -634,6 +701,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
 {
     if (!h || n < 0 || !ld_ok(n, ldl) || !ld_ok(n, ldlb) || (n > 0 && (!L || !Lbar)))
         return GPC_ERR_ARG;
+    if (overlap(L, n, n, ldl, Lbar, n, n, ldlb)) return GPC_ERR_ARG;
     if (n == 0) return GPC_OK;
     hipStream_t s = h->stream;
     const int b = std::min(block_of(h), kDefaultBlock);   // the adjoint's blocks stop at 256
@@ -843,6 +911,7 @@ gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const
     if (!h || (trans != GPC_NOTRANS && trans != GPC_TRANS) || n < 0 || nrhs < 0 || !ld_ok(n, ldl) ||
         !ld_ok(nrhs, ldb) || (n > 0 && nrhs > 0 && (!L || !B)))
         return GPC_ERR_ARG;
+    if (overlap(L, n, n, ldl, B, n, nrhs, ldb)) return GPC_ERR_ARG;
     if (n == 0 || nrhs == 0) return GPC_OK;
     hipStream_t s = h->stream;
     const int b = solve_block(n);
@@ -855,7 +924,7 @@ gpc_status gpc_trsm(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const
     double* Y = Cpl + n_dinv;
     GPC_HIP(h, diag_block_inverses(s, n, b, L, ldl, Dinv, Cpl));
     GPC_HIP(h, trsm_couplings(s, trans, n, L, ldl, Dinv, b, Cpl));
-    GPC_HIP(h, trsm_blocked(s, trans, n, nrhs, L, ldl, Dinv, Cpl, b, B, ldb, Y, h->cus, h->opt.test_flags));
+    GPC_HIP(h, trsm_blocked(s, trans, n, nrhs, L, ldl, Dinv, Cpl, b, B, ldb, Y, h->cus, h->opt.test_flags, h->status_dev));
     return GPC_OK;
 }
 
@@ -881,6 +950,10 @@ gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, 
 {
     if (!h || n < 0 || !ld_ok(n, ldl) || !logdet_out || !f_out || (n > 0 && (!L || !y || !z || !alpha)))
         return GPC_ERR_ARG;
+    if (overlap(z, 1, n, n, alpha, 1, n, n) || overlap(z, 1, n, n, L, n, n, ldl) ||
+        overlap(alpha, 1, n, n, L, n, n, ldl) || overlap(z, 1, n, n, y, 1, n, n) ||
+        overlap(alpha, 1, n, n, y, 1, n, n))
+        return GPC_ERR_ARG;
     hipStream_t s = h->stream;
     if (n > 0) {
         const int b = solve_block(n);
@@ -896,9 +969,9 @@ gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, 
         GPC_HIP(h, trsm_couplings(s, 0, n, L, ldl, Dinv, b, Cf));
         GPC_HIP(h, trsm_couplings(s, 1, n, L, ldl, Dinv, b, Cb));
         GPC_HIP(h, vec_copy(s, n, y, z));
-        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, z, 1, Y, h->cus, h->opt.test_flags));
+        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, z, 1, Y, h->cus, h->opt.test_flags, h->status_dev));
         GPC_HIP(h, vec_copy(s, n, z, alpha));
-        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, alpha, 1, Y, h->cus, h->opt.test_flags));
+        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, alpha, 1, Y, h->cus, h->opt.test_flags, h->status_dev));
     }
     GPC_HIP(h, logdet(s, n, L, ldl, logdet_out));
     GPC_HIP(h, gp_value(s, n, z, logdet_out, f_out));
@@ -909,6 +982,9 @@ gpc_status gpc_gp_lbar(gpc_handle* h, int64_t n, const double* L, int64_t ldl, c
                        const double* z, double* Lbar, int64_t ldlb)
 {
     if (!h || n < 0 || !ld_ok(n, ldl) || !ld_ok(n, ldlb) || (n > 0 && (!L || !alpha || !z || !Lbar)))
+        return GPC_ERR_ARG;
+    if (overlap(Lbar, n, n, ldlb, L, n, n, ldl) || overlap(Lbar, n, n, ldlb, alpha, 1, n, n) ||
+        overlap(Lbar, n, n, ldlb, z, 1, n, n))
         return GPC_ERR_ARG;
     GPC_HIP(h, gp_lbar(h->stream, n, L, ldl, alpha, z, Lbar, ldlb));
     return GPC_OK;
@@ -935,6 +1011,8 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
 {
     if (!h || n < 0 || !ld_ok(n, ldk) || !ld_ok(n, ldl) || !iters || !eta ||
         (n > 0 && (!K || !L || !y || !x)))
+        return GPC_ERR_ARG;
+    if (overlap(x, 1, n, n, K, n, n, ldk) || overlap(x, 1, n, n, L, n, n, ldl) || overlap(x, 1, n, n, y, 1, n, n))
         return GPC_ERR_ARG;
     hipStream_t s = h->stream;
     if (n == 0) {
@@ -968,16 +1046,23 @@ gpc_status gpc_solve_refined(gpc_handle* h, int64_t n, const double* K, int64_t 
     while (it < maxit) {
         ++it;
         GPC_HIP(h, vec_copy(s, n, r, d));
-        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, d, 1, Y, h->cus, h->opt.test_flags));
-        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, d, 1, Y, h->cus, h->opt.test_flags));
+        GPC_HIP(h, trsm_blocked(s, 0, n, 1, L, ldl, Dinv, Cf, b, d, 1, Y, h->cus, h->opt.test_flags, h->status_dev));
+        GPC_HIP(h, trsm_blocked(s, 1, n, 1, L, ldl, Dinv, Cb, b, d, 1, Y, h->cus, h->opt.test_flags, h->status_dev));
         GPC_HIP(h, vec_axpy(s, n, d, x));
         if (it == 1)   // the row sums of |K| for eta come from the same pass over K
             GPC_HIP(h, symv_lower_abs(s, n, K, ldk, x, y, -1.0, r, rowabs, part));
         else
             GPC_HIP(h, symv_lower(s, n, K, ldk, x, 0, y, -1.0, r, part));
         GPC_HIP(h, refine_eta(s, n, r, x, y, rowabs, eta));
+        uint32_t rec = 0;
         GPC_HIP(h, hipMemcpyAsync(&eta_h, eta, sizeof(double), hipMemcpyDeviceToHost, s));
+        GPC_HIP(h, hipMemcpyAsync(&rec, h->status_dev, sizeof(rec), hipMemcpyDeviceToHost, s));
         GPC_HIP(h, hipStreamSynchronize(s));
+        if (rec != 0) {   // a sweep ran out of time: x is not a solution
+            GPC_HIP(h, fill_i32(s, (int32_t*)h->status_dev, 0));
+            GPC_HIP(h, fill_i32(s, iters, it));
+            return GPC_ERR_SWEEP;
+        }
         if (eta_h <= h->opt.refine_tol) break;
     }
     GPC_HIP(h, fill_i32(s, iters, it));
@@ -998,14 +1083,24 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
     if (nb == 0) return GPC_OK;
     if (h->opt.precision == GPC_MIXED) mode |= 4;   // FP32 trailing and B-bar / R-bar products
     hipStream_t s = h->stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    GPC_HIP(h, hipStreamIsCapturing(s, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
     std::vector<int32_t> blocks(h->tune_block, h->tune_block + kTuneBuckets);
     BatchPlan* p = h->plan;
     const bool same = p && p->mode == mode && p->A == A && p->Lb == Lb && p->info == info &&
                       p->blocks == blocks && p->n.size() == (size_t)nb &&
                       std::equal(p->n.begin(), p->n.end(), n_host) && std::equal(p->off.begin(), p->off.end(), off_host);
     if (!same) {
+        // a new plan waits for the stream and allocates: not possible while
+        // the caller captures
+        if (capturing) {
+            snprintf(h->err, sizeof(h->err),
+                     "no batched plan for these sizes, offsets and pointers: make the same call once before capturing");
+            return GPC_ERR_CAPTURE;
+        }
         GPC_HIP(h, hipStreamSynchronize(s));
-        free_plan(p);
+        retire_plan(h);
         h->plan = p = new BatchPlan();
         p->mode = mode;
         p->A = A;
@@ -1043,13 +1138,13 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
         if (ce != hipSuccess) return hip_fail(h, ce, "hipStreamEndCapture");
         GPC_HIP(h, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     }
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    GPC_HIP(h, hipStreamIsCapturing(s, &cs));
     Traced t(h, GPC_K_BATCHED, p->flops, 0.0);
-    if (cs == hipStreamCaptureStatusNone) {
+    if (!capturing) {
         GPC_HIP(h, hipGraphLaunch(p->exec, s));
     } else {
-        // the caller is capturing: record the launch into its graph instead
+        // the caller is capturing: record the launch into its graph instead;
+        // the plan's buffers then stay allocated until gpc_destroy
+        p->pinned = true;
         GPC_HIP(h, gpc::batched_launch(s, nb, p->d_tasks, A, Lb, info, p->d_counter, p->d_ws, p->wgs, mode));
     }
     return GPC_OK;
@@ -1083,6 +1178,9 @@ gpc_status gpc_autotune_batched(gpc_handle* h, const char* cache_path)
 {
     if (!h) return GPC_ERR_ARG;
     hipStream_t s = h->stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    GPC_HIP(h, hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return GPC_ERR_CAPTURE;
     const int mids[kTuneBuckets] = {80, 192, 384, 768, 1024};
     const int cnt = 16;
     for (int bk = 0; bk < kTuneBuckets; ++bk) {
@@ -1120,8 +1218,7 @@ gpc_status gpc_autotune_batched(gpc_handle* h, const char* cache_path)
         }
         h->tune_block[bk] = best;
         GPC_HIP(h, hipStreamSynchronize(s));
-        free_plan(h->plan);
-        h->plan = nullptr;
+        retire_plan(h);
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         hipFree(A);

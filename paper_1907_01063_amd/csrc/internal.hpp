@@ -98,12 +98,13 @@ hipError_t trsm_couplings(hipStream_t s, int trans, int64_t n, const double* L, 
 // B <- L^-1 B (trans 0) or L^-T B (trans 1) by block steps with Dinv and the
 // couplings of the same direction (block b = 128 or 256): one launch for a
 // single right-hand side (cus: compute units, sizes its grid; fail: start it
-// with its error flag raised), else one launch per block step and group of
+// with its error flag raised; rec: device word set to 1 if the sweep fails,
+// never cleared here), else one launch per block step and group of
 // right-hand sides.  Y: workspace of trsm_workspace(n) doubles.
 int64_t trsm_workspace(int64_t n);
 hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L,
                         int64_t ldl, const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb,
-                        double* Y, int cus, int fail);
+                        double* Y, int cus, int fail, uint32_t* rec);
 // *out = 2 * sum_i log L_ii (fixed summation order).
 hipError_t logdet(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* out);
 

@@ -309,22 +309,28 @@ __global__ void __launch_bounds__(256) logdet_kernel(int64_t n, const double* L,
 // workgroups are resident.
 //
 // Hand-over.  y' and the solution are written to workspace vectors that
-// start filled with a signalling NaN, a value arithmetic never produces: the
-// chain items wait for their operands by reading them until none is that
-// value.  To keep that polling to the few items near the front of the sweep,
-// everything else waits on per-step counters (one word per workgroup) that
-// the chain items raise once their stores are complete: a chain item of step
-// q waits for step q-2 to be complete before it reads its operands, and the
-// strips wait on the counters for every block but their last (the one the
-// next chain item waits for), which they read like the chain items.  Every access of data written in the sweep is device-scope,
-// coherent across the per-XCD L2 caches by itself, so no cache maintenance
-// (L2 write-back or invalidate) is needed, and no plain load leaves a copy of
-// such data in an L2.  Every wait is bounded: after kSpinLimit polls the
-// sweep raises an error flag, later waits return at once and the chain items
-// write NaN, so a sweep that could not finish shows in its result.  The
-// reduction orders are fixed, so results repeat bit for bit.
+// start filled with a signalling NaN, a value arithmetic never produces.
+// Every value one workgroup reads from another is read from such a vector
+// with device-scope loads until it is no longer that value, so each read is
+// its own signal: no read relies on the order in which two different
+// locations become visible, and no cache maintenance (L2 write-back or
+// invalidate) is needed (device-scope accesses are coherent across the
+// per-XCD L2 caches, and no plain load leaves a copy of such data in an L2).
+// Per-step counters (one word per workgroup), raised by the chain items once
+// their stores have completed, only throttle the polling: a chain item of
+// step q waits on the counter of step q-2 before it polls its operands, and
+// a strip waits on the counter of each block but its last before it reads
+// that block's solution (still checking every value).  So only the few items
+// near the front of the sweep poll data, the rest poll one word each.
+//
+// Every wait is bounded in time (kWaitTicks of the 100 MHz constant clock):
+// a wait that runs out raises the sweep's error flag and the caller's
+// failure record; later waits then return at once and the chain items write
+// NaN, so a sweep that could not finish ends promptly, shows in its result
+// and is reported to the host (the library reads the record).  The reduction
+// orders are fixed, so results repeat bit for bit.
 
-constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr uint64_t kWaitTicks = 10000000ull;           // 100 ms at 100 MHz
 constexpr int kCtrlStride = 32;                        // words between two counters (128 B)
 constexpr uint64_t kPending = 0x7FF0DEADBEEF0001ull;   // signalling NaN: not yet written
 
@@ -337,6 +343,10 @@ __device__ __forceinline__ uint32_t load_agent(const uint32_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ double ld_dev(const double* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -346,14 +356,42 @@ __device__ __forceinline__ void st_dev(double* p, double v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded wait of one thread: true while it may go on polling (the limit
-// raises the error flag; a raised flag ends every wait).
-__device__ __forceinline__ bool keep_polling(uint32_t& it, uint32_t* err)
+// The sweep's shared words: its error flag (reset by every sweep) and the
+// caller's failure record (kept across sweeps until the host clears it).
+struct SweepFlags {
+    uint32_t* err;
+    uint32_t* rec;
+};
+
+__device__ __forceinline__ void raise_failure(const SweepFlags& f)
 {
-    if ((++it & 255u) == 0) {
-        if (load_agent(err)) return false;
-        if (it >= kSpinLimit) {
-            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    store_agent(f.err, 1u);
+    store_agent(f.rec, 1u);
+}
+
+// True if the sweep has failed; then the caller's record is (also) raised,
+// so that a sweep started with its flag raised is reported as well.
+__device__ __forceinline__ bool failed(const SweepFlags& f)
+{
+    if (!load_agent(f.err)) return false;
+    store_agent(f.rec, 1u);
+    return true;
+}
+
+__device__ __forceinline__ uint64_t now_ticks() { return (uint64_t)wall_clock64(); }
+
+// Bounded wait of one thread: true while it may go on polling.  The clock is
+// read every 16 polls (the first reading sets the deadline); past the
+// deadline the flags are raised, and a raised flag ends every wait.
+__device__ __forceinline__ bool keep_polling(uint32_t& it, uint64_t& deadline, const SweepFlags& f)
+{
+    if ((++it & 15u) == 0) {
+        if (load_agent(f.err)) return false;
+        const uint64_t t = now_ticks();
+        if (deadline == 0) {
+            deadline = t + kWaitTicks;
+        } else if (t > deadline) {
+            raise_failure(f);
             return false;
         }
     }
@@ -364,15 +402,16 @@ __device__ __forceinline__ bool keep_polling(uint32_t& it, uint32_t* err)
 // One thread: *p once it is no longer kPending (or the sweep has failed).
 // Two reads are kept in flight, the older one checked while the newer is on
 // its way, so a value is seen about half a round trip sooner than with one.
-__device__ double await_value(const double* p, uint32_t* err)
+__device__ double await_value(const double* p, const SweepFlags& f)
 {
     uint32_t it = 0;
+    uint64_t deadline = 0;
     double a = ld_dev(p);
     double b = ld_dev(p);
     for (;;) {
-        if (__builtin_bit_cast(uint64_t, a) != kPending || !keep_polling(it, err)) return a;
+        if (__builtin_bit_cast(uint64_t, a) != kPending || !keep_polling(it, deadline, f)) return a;
         a = ld_dev(p);
-        if (__builtin_bit_cast(uint64_t, b) != kPending || !keep_polling(it, err)) return b;
+        if (__builtin_bit_cast(uint64_t, b) != kPending || !keep_polling(it, deadline, f)) return b;
         b = ld_dev(p);
     }
 }
@@ -384,17 +423,21 @@ __device__ double await_value(const double* p, uint32_t* err)
 // cycling through the barriers) for the counter updates.
 __device__ __forceinline__ bool first_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0; }
 
-// All threads: returns once *ctr >= target (or the sweep has failed); loads
-// by ld_dev issued afterwards see the stores published before.
-__device__ void wait_count(const uint32_t* ctr, uint32_t target, uint32_t* err)
+// All threads: returns once *ctr >= target, or the sweep has failed, or the
+// wait ran out of time (then the flags are raised).
+__device__ void wait_count(const uint32_t* ctr, uint32_t target, const SweepFlags& f)
 {
     if (first_wave()) {
         uint32_t it = 0;
+        uint64_t deadline = 0;
         while (__builtin_amdgcn_readfirstlane(load_agent(ctr)) < target) {
-            if ((++it & 255u) == 0) {
-                if (__builtin_amdgcn_readfirstlane(load_agent(err))) break;
-                if (it >= kSpinLimit) {
-                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((++it & 15u) == 0) {
+                if (__builtin_amdgcn_readfirstlane(load_agent(f.err))) break;
+                const uint64_t t = now_ticks();   // a scalar read: uniform
+                if (deadline == 0) {
+                    deadline = t + kWaitTicks;
+                } else if (t > deadline) {
+                    raise_failure(f);
                     break;
                 }
             }
@@ -436,7 +479,7 @@ __device__ uint32_t next_ticket(uint32_t* ctrl)
 // order and are combined in a fixed tree.
 template <int BS>
 __device__ void fwd_strip(int64_t n, int64_t q, int r, const double* L, int64_t ldl, const double* B, int64_t ldb,
-                          const double* Zs, double* Yp, uint32_t* ctrl, double* zs)
+                          const double* Zs, double* Yp, uint32_t* ctrl, const SweepFlags& f, double* zs)
 {
     constexpr int SR = 8192 / BS, RPT = SR / 8, CPT = BS / 32, K = BS / 16;
     static_assert(RPT * CPT == 32, "32 values of L per thread and block");
@@ -462,12 +505,10 @@ __device__ void fwd_strip(int64_t n, int64_t q, int r, const double* L, int64_t 
 #pragma unroll
             for (int c = 0; c < CPT; ++c) v[i][c] = row < n ? lr[32 * c] : 0.0;
         }
-        if (p + 2 < q) {
-            wait_count(zdone(ctrl, p), K, ctrl + kCtrlStride);
-            if ((int)threadIdx.x < BS) zs[threadIdx.x] = ld_dev(Zs + p * BS + threadIdx.x);
-        } else if ((int)threadIdx.x < BS) {   // last block: on the chain's path, read as it lands
-            zs[threadIdx.x] = await_value(Zs + p * BS + threadIdx.x, ctrl + kCtrlStride);
-        }
+        // all blocks but the last: throttled by the step counter first; the
+        // last is on the chain's path and is read as it lands
+        if (p + 2 < q) wait_count(zdone(ctrl, p), K, f);
+        if ((int)threadIdx.x < BS) zs[threadIdx.x] = await_value(Zs + p * BS + threadIdx.x, f);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
@@ -493,14 +534,14 @@ __device__ void fwd_strip(int64_t n, int64_t q, int r, const double* L, int64_t 
 // loaded before the waits.
 template <int BS>
 __device__ void fwd_chain(int64_t n, int64_t q, int c, const double* Dinv, const double* Cf, double* B,
-                          int64_t ldb, double* Zs, const double* Yp, uint32_t* ctrl, double* ys, double* zs)
+                          int64_t ldb, double* Zs, const double* Yp, uint32_t* ctrl, const SweepFlags& f, double* ys,
+                          double* zs)
 {
     const int bq = (int)min((int64_t)BS, n - q * BS);
     const int sl = threadIdx.x & 15;
     const int i = 16 * c + (int)(threadIdx.x >> 4);
     const double* Dn = Dinv + q * BS * BS;
     const double* Cn = Cf + q * BS * BS;
-    uint32_t* err = ctrl + kCtrlStride;
     double dv[BS / 16], cv[BS / 16];
 #pragma unroll
     for (int m = 0; m < BS / 16; ++m) {
@@ -510,15 +551,15 @@ __device__ void fwd_chain(int64_t n, int64_t q, int c, const double* Dinv, const
     }
     // until step q-2 is complete y'_q is far off: wait on its counter (one
     // word per workgroup) before reading the data itself
-    if (q >= 2) wait_count(zdone(ctrl, q - 2), BS / 16, err);
+    if (q >= 2) wait_count(zdone(ctrl, q - 2), BS / 16, f);
     if ((int)threadIdx.x < BS)
-        ys[threadIdx.x] = (int)threadIdx.x < bq ? await_value(Yp + q * BS + threadIdx.x, err) : 0.0;
+        ys[threadIdx.x] = (int)threadIdx.x < bq ? await_value(Yp + q * BS + threadIdx.x, f) : 0.0;
     __syncthreads();
     double t = 0.0;
 #pragma unroll
     for (int m = 0; m < BS / 16; ++m) t += dv[m] * ys[sl + 16 * m];
     if (q >= 1) {
-        if ((int)threadIdx.x < BS) zs[threadIdx.x] = await_value(Zs + (q - 1) * BS + threadIdx.x, err);
+        if ((int)threadIdx.x < BS) zs[threadIdx.x] = await_value(Zs + (q - 1) * BS + threadIdx.x, f);
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < BS / 16; ++m) t -= cv[m] * zs[sl + 16 * m];
@@ -529,7 +570,7 @@ __device__ void fwd_chain(int64_t n, int64_t q, int c, const double* Dinv, const
         t = (sl & w) ? o + t : t + o;
     }
     if (sl == 0 && i < bq) {
-        const double z = load_agent(err) ? __builtin_nan("") : t;
+        const double z = failed(f) ? __builtin_nan("") : t;
         st_dev(Zs + q * BS + i, z);
         B[(q * BS + i) * ldb] = z;
     }
@@ -541,7 +582,8 @@ __device__ void fwd_chain(int64_t n, int64_t q, int c, const double* Dinv, const
 // sums run over p in decreasing order and are combined in group order.
 template <int BS>
 __device__ void bwd_strip(int64_t n, int64_t nblk, int64_t q, int r, const double* L, int64_t ldl, const double* B,
-                          int64_t ldb, const double* Zs, double* Yp, uint32_t* ctrl, double* xs, double* red)
+                          int64_t ldb, const double* Zs, double* Yp, uint32_t* ctrl, const SweepFlags& f, double* xs,
+                          double* red)
 {
     constexpr int SR = 8192 / BS, NG = 256 / SR, K = BS / 16;
     const int j = threadIdx.x % SR, g = threadIdx.x / SR;
@@ -555,12 +597,9 @@ __device__ void bwd_strip(int64_t n, int64_t nblk, int64_t q, int r, const doubl
         const double* lc = L + (p * BS + g) * ldl + (live ? col : 0);
 #pragma unroll
         for (int k = 0; k < 32; ++k) v[k] = (live && g + NG * k < bp) ? lc[(int64_t)NG * k * ldl] : 0.0;
-        if (p > q + 2) {
-            wait_count(zdone(ctrl, p), K, ctrl + kCtrlStride);
-            if ((int)threadIdx.x < BS) xs[threadIdx.x] = (int)threadIdx.x < bp ? ld_dev(Zs + p * BS + threadIdx.x) : 0.0;
-        } else if ((int)threadIdx.x < BS) {   // last block: on the chain's path, read as it lands
-            xs[threadIdx.x] = (int)threadIdx.x < bp ? await_value(Zs + p * BS + threadIdx.x, ctrl + kCtrlStride) : 0.0;
-        }
+        if (p > q + 2) wait_count(zdone(ctrl, p), K, f);   // as in the forward strip
+        if ((int)threadIdx.x < BS)
+            xs[threadIdx.x] = (int)threadIdx.x < bp ? await_value(Zs + p * BS + threadIdx.x, f) : 0.0;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 32; ++k) acc += v[k] * xs[g + NG * k];
@@ -583,8 +622,8 @@ __device__ void bwd_strip(int64_t n, int64_t nblk, int64_t q, int r, const doubl
 // order.
 template <int BS>
 __device__ void bwd_chain(int64_t n, int64_t nblk, int64_t q, int c, const double* Dinv, const double* Cb, double* B,
-                          int64_t ldb, double* Zs, const double* Yp, uint32_t* ctrl, double* ys, double* xs,
-                          double* red)
+                          int64_t ldb, double* Zs, const double* Yp, uint32_t* ctrl, const SweepFlags& f, double* ys,
+                          double* xs, double* red)
 {
     const int bq = (int)min((int64_t)BS, n - q * BS);
     const int bc = q + 1 < nblk ? (int)min((int64_t)BS, n - (q + 1) * BS) : 0;
@@ -592,7 +631,6 @@ __device__ void bwd_chain(int64_t n, int64_t nblk, int64_t q, int c, const doubl
     const int i = 16 * c + l;
     const double* Dp = Dinv + q * BS * BS;
     const double* Cp = Cb + q * BS * BS;
-    uint32_t* err = ctrl + kCtrlStride;
     double dv[BS / 16], cv[BS / 16];
 #pragma unroll
     for (int m = 0; m < BS / 16; ++m) {
@@ -600,16 +638,16 @@ __device__ void bwd_chain(int64_t n, int64_t nblk, int64_t q, int c, const doubl
         dv[m] = (i < bq && t >= i && t < bq) ? Dp[(int64_t)t * BS + i] : 0.0;   // (Dinv^T)[i][t], Dinv lower
         cv[m] = (i < bq && t < bc) ? Cp[(int64_t)t * BS + i] : 0.0;
     }
-    if (q + 2 < nblk) wait_count(zdone(ctrl, q + 2), BS / 16, err);   // as in the forward chain
+    if (q + 2 < nblk) wait_count(zdone(ctrl, q + 2), BS / 16, f);   // as in the forward chain
     if ((int)threadIdx.x < BS)
-        ys[threadIdx.x] = (int)threadIdx.x < bq ? await_value(Yp + q * BS + threadIdx.x, err) : 0.0;
+        ys[threadIdx.x] = (int)threadIdx.x < bq ? await_value(Yp + q * BS + threadIdx.x, f) : 0.0;
     __syncthreads();
     double part = 0.0;
 #pragma unroll
     for (int m = 0; m < BS / 16; ++m) part += dv[m] * ys[g + 16 * m];
     if (bc > 0) {
         if ((int)threadIdx.x < BS)
-            xs[threadIdx.x] = (int)threadIdx.x < bc ? await_value(Zs + (q + 1) * BS + threadIdx.x, err) : 0.0;
+            xs[threadIdx.x] = (int)threadIdx.x < bc ? await_value(Zs + (q + 1) * BS + threadIdx.x, f) : 0.0;
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < BS / 16; ++m) part -= cv[m] * xs[g + 16 * m];
@@ -619,7 +657,7 @@ __device__ void bwd_chain(int64_t n, int64_t nblk, int64_t q, int c, const doubl
     if (threadIdx.x < 16 && 16 * c + (int)threadIdx.x < bq) {
         double v = 0.0;
         for (int gg = 0; gg < 16; ++gg) v += red[gg * 16 + threadIdx.x];
-        const double x = load_agent(err) ? __builtin_nan("") : v;
+        const double x = failed(f) ? __builtin_nan("") : v;
         st_dev(Zs + q * BS + 16 * c + threadIdx.x, x);
         B[(q * BS + 16 * c + threadIdx.x) * ldb] = x;
     }
@@ -628,14 +666,15 @@ __device__ void bwd_chain(int64_t n, int64_t nblk, int64_t q, int c, const doubl
 
 // One launch of a whole sweep (trans 0: B <- L^-1 B, 1: B <- L^-T B) for one
 // right-hand side.  Yp, Zs: n doubles each, filled with kPending; ctrl:
-// ctrl_words(nblk) zeroed words.
+// ctrl_words(nblk) zeroed words; rec: the caller's failure record.
 template <int BS, int TRANS>
 __global__ void __launch_bounds__(256, 4)
 trsv_sweep1(int64_t n, int64_t nblk, const double* L, int64_t ldl, const double* Dinv, const double* Cpl,
-            double* B, int64_t ldb, double* Yp, double* Zs, uint32_t* ctrl)
+            double* B, int64_t ldb, double* Yp, double* Zs, uint32_t* ctrl, uint32_t* rec)
 {
     constexpr int NS = BS * BS / 8192, K = BS / 16, P = NS + K;
     __shared__ double s_a[BS], s_b[BS], s_red[256];
+    const SweepFlags f{ctrl + kCtrlStride, rec};
     const uint32_t total = (uint32_t)(nblk * P);
     for (;;) {
         const uint32_t t = next_ticket(ctrl);
@@ -644,11 +683,11 @@ trsv_sweep1(int64_t n, int64_t nblk, const double* L, int64_t ldl, const double*
         const int r = (int)(t % P);
         const int64_t q = TRANS ? nblk - 1 - step : step;
         if (!TRANS) {
-            if (r < NS) fwd_strip<BS>(n, q, r, L, ldl, B, ldb, Zs, Yp, ctrl, s_a);
-            else fwd_chain<BS>(n, q, r - NS, Dinv, Cpl, B, ldb, Zs, Yp, ctrl, s_a, s_b);
+            if (r < NS) fwd_strip<BS>(n, q, r, L, ldl, B, ldb, Zs, Yp, ctrl, f, s_a);
+            else fwd_chain<BS>(n, q, r - NS, Dinv, Cpl, B, ldb, Zs, Yp, ctrl, f, s_a, s_b);
         } else {
-            if (r < NS) bwd_strip<BS>(n, nblk, q, r, L, ldl, B, ldb, Zs, Yp, ctrl, s_a, s_red);
-            else bwd_chain<BS>(n, nblk, q, r - NS, Dinv, Cpl, B, ldb, Zs, Yp, ctrl, s_a, s_b, s_red);
+            if (r < NS) bwd_strip<BS>(n, nblk, q, r, L, ldl, B, ldb, Zs, Yp, ctrl, f, s_a, s_red);
+            else bwd_chain<BS>(n, nblk, q, r - NS, Dinv, Cpl, B, ldb, Zs, Yp, ctrl, f, s_a, s_b, s_red);
         }
         // every item's lane-dependent tail joins here, so the loop has one
         // back edge that all lanes take together
@@ -740,7 +779,7 @@ namespace {
 // one launch of at most four workgroups per compute unit.
 template <int BS>
 hipError_t sweep1(hipStream_t s, int trans, int64_t n, const double* L, int64_t ldl, const double* Dinv,
-                  const double* Cpl, double* B, int64_t ldb, double* Y, int cus, int fail)
+                  const double* Cpl, double* B, int64_t ldb, double* Y, int cus, int fail, uint32_t* rec)
 {
     constexpr int P = BS * BS / 8192 + BS / 16;
     const int64_t nblk = (n + BS - 1) / BS;
@@ -753,16 +792,17 @@ hipError_t sweep1(hipStream_t s, int trans, int64_t n, const double* L, int64_t 
     const int64_t grid = std::min<int64_t>(nblk * P, 4 * (int64_t)std::max(cus, 1));
     if (!trans)
         hipLaunchKernelGGL((trsv_sweep1<BS, 0>), dim3((unsigned)grid), dim3(256), 0, s, n, nblk, L, ldl, Dinv, Cpl, B,
-                           ldb, Yp, Zs, ctrl);
+                           ldb, Yp, Zs, ctrl, rec);
     else
         hipLaunchKernelGGL((trsv_sweep1<BS, 1>), dim3((unsigned)grid), dim3(256), 0, s, n, nblk, L, ldl, Dinv, Cpl, B,
-                           ldb, Yp, Zs, ctrl);
+                           ldb, Yp, Zs, ctrl, rec);
     return hipGetLastError();
 }
 
 template <int BS>
 hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
-                 const double* Dinv, const double* Cpl, double* B, int64_t ldb, double* Y, int cus, int fail)
+                 const double* Dinv, const double* Cpl, double* B, int64_t ldb, double* Y, int cus, int fail,
+                 uint32_t* rec)
 {
     constexpr int kLook = BS / 16;
     const int64_t nblk = (n + BS - 1) / BS;
@@ -772,7 +812,7 @@ hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double
         const int nr = (int)std::min<int64_t>(kRhsGroup, nrhs - c0);
         double* Bc = B + c0;
         if (nr == 1) {
-            const hipError_t e = sweep1<BS>(s, trans, n, L, ldl, Dinv, Cpl, Bc, ldb, Y, cus, fail);
+            const hipError_t e = sweep1<BS>(s, trans, n, L, ldl, Dinv, Cpl, Bc, ldb, Y, cus, fail, rec);
             if (e != hipSuccess) return e;
             continue;
         }
@@ -803,10 +843,11 @@ hipError_t sweep(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double
 
 hipError_t trsm_blocked(hipStream_t s, int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
                         const double* Dinv, const double* Cpl, int b, double* B, int64_t ldb, double* Y, int cus,
-                        int fail)
+                        int fail, uint32_t* rec)
 {
-    if (b == 128) return sweep<128>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus, fail);
-    if (b == 256) return sweep<256>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus, fail);
+    if (!rec) return hipErrorInvalidValue;
+    if (b == 128) return sweep<128>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus, fail, rec);
+    if (b == 256) return sweep<256>(s, trans, n, nrhs, L, ldl, Dinv, Cpl, B, ldb, Y, cus, fail, rec);
     return hipErrorInvalidValue;
 }
 

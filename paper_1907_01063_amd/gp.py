@@ -33,7 +33,10 @@ class GPMarginalLogLik(torch.autograd.Function):
     recompute_L: do not keep L between forward and backward; refactor it
     (same kernels, same inputs, so the gradient is bitwise the same).
     check: read the factor's info flag (one device sync) and raise
-    NotPositiveDefiniteError on failure.
+    NotPositiveDefiniteError on failure; in the mixed form a lost pivot first
+    makes the covariance be generated again and factored in FP64 (backward
+    then uses FP64 too).  Also raises GpcError if a solve sweep ran out of
+    time.
     """
 
     @staticmethod
@@ -45,9 +48,17 @@ class GPMarginalLogLik(torch.autograd.Function):
         L, info = _factor(H, X, th, precision)
         if check:
             col = int(info.item())
+            if col != 0 and precision == GPC_MIXED:
+                # the FP32-updated Schur complement lost definiteness: the
+                # covariance is generated again and factored in FP64
+                precision = GPC_FP64
+                L, info = _factor(H, X, th, precision)
+                col = int(info.item())
             if col != 0:
                 raise NotPositiveDefiniteError(col)
         f, z, alpha, _ = H.gp_value(L, y)
+        if check:
+            H.check()   # raises if a solve sweep ran out of time
         ctx.H, ctx.precision, ctx.recompute = H, precision, recompute_L
         ctx.save_for_backward(X, th, z, alpha, None if recompute_L else L)
         return f

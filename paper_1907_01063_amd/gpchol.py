@@ -17,13 +17,14 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpchol.so")
 
-GPC_OK, GPC_ERR_ARG, GPC_ERR_NO_DEVICE, GPC_ERR_ARCH, GPC_ERR_HIP, GPC_ERR_REFINE, GPC_ERR_ALLOC = range(7)
+(GPC_OK, GPC_ERR_ARG, GPC_ERR_NO_DEVICE, GPC_ERR_ARCH, GPC_ERR_HIP, GPC_ERR_REFINE, GPC_ERR_ALLOC,
+ GPC_ERR_SWEEP, GPC_ERR_CAPTURE) = range(9)
 GPC_FP64, GPC_MIXED = 0, 1
 GPC_NOTRANS, GPC_TRANS = 0, 1
 
 # Every symbol the header declares, in declaration order.
 EXPORTS = (
-    "gpc_create", "gpc_destroy", "gpc_set_stream", "gpc_set_options", "gpc_get_options",
+    "gpc_create", "gpc_destroy", "gpc_set_stream", "gpc_check", "gpc_set_options", "gpc_get_options",
     "gpc_factor", "gpc_get_fallback", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
     "gpc_solve_refined", "gpc_gp_kgen_se", "gpc_gp_value", "gpc_gp_lbar", "gpc_gp_hypergrad_se",
     "gpc_factor_batched", "gpc_adjoint_batched", "gpc_factor_adjoint_batched", "gpc_autotune_batched",
@@ -67,6 +68,7 @@ def load_library(path: str = LIB_PATH):
         "gpc_create": [ctypes.POINTER(_vp), _vp],
         "gpc_destroy": [_vp],
         "gpc_set_stream": [_vp, _vp],
+        "gpc_check": [_vp],
         "gpc_set_options": [_vp, ctypes.POINTER(gpc_options)],
         "gpc_get_options": [_vp, ctypes.POINTER(gpc_options)],
         "gpc_factor": [_vp, _i64, _vp, _i64, _vp],
@@ -143,6 +145,12 @@ class Handle:
 
     def _sync_stream(self):
         self.lib.gpc_set_stream(self.h, _vp(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def check(self):
+        """Wait for the stream; raise GpcError(GPC_ERR_SWEEP) if a one-launch
+        solve sweep of this handle ran out of time since the last check."""
+        self._sync_stream()
+        self._check(self.lib.gpc_check(self.h), "gpc_check")
 
     def options(self) -> gpc_options:
         o = gpc_options()

@@ -14,6 +14,13 @@ def say(msg: str):
     sys.stdout.flush()
 
 
+def progress(msg: str):
+    """A line on the process's real stderr (not captured by pytest), for the
+    long steps of the full-size tests."""
+    sys.__stderr__.write(f"[progress] {msg}\n")
+    sys.__stderr__.flush()
+
+
 def dev(a: np.ndarray) -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 

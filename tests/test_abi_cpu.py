@@ -42,12 +42,13 @@ def test_null_handle_and_bad_arguments_rejected():
     assert lib.gpc_create(None, None) == E
     assert lib.gpc_set_options(None, None) == E
     assert lib.gpc_get_fallback(None, None) == E
+    assert lib.gpc_check(None) == E
 
 
 def test_status_strings():
     lib = gpchol.load_library()
-    for code in range(7):
-        assert lib.gpc_status_string(code)
+    for code in range(9):
+        assert lib.gpc_status_string(code) != b"unknown status"
     assert lib.gpc_status_string(99) == b"unknown status"
 
 

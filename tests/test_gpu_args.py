@@ -1,0 +1,62 @@
+"""Argument checks that need a live handle (no kernel runs in these cases):
+leading dimensions above 2^20 and outputs that overlap inputs are rejected
+with GPC_ERR_ARG before anything is enqueued.  Every buffer is sized for the
+leading dimension it is passed with, so even a missed check would stay in
+bounds."""
+import ctypes
+
+import pytest
+import torch
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+BIG = (1 << 20) + 1
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1907_01063_amd import Handle
+    return Handle()
+
+
+def test_leading_dimension_above_limit_rejected(H):
+    from paper_1907_01063_amd.gpchol import GPC_ERR_ARG, GPC_OK
+    lib, h = H.lib, H.h
+    A = torch.zeros(4 * BIG, dtype=torch.float64, device="cuda")   # 4 rows of BIG doubles
+    Lb = torch.zeros(4 * BIG, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    y = torch.zeros(4 * BIG, dtype=torch.float64, device="cuda")
+    H._sync_stream()
+    assert lib.gpc_factor(h, 4, A.data_ptr(), BIG, info.data_ptr()) == GPC_ERR_ARG
+    assert lib.gpc_adjoint(h, 4, A.data_ptr(), BIG, Lb.data_ptr(), 4) == GPC_ERR_ARG
+    assert lib.gpc_adjoint(h, 4, A.data_ptr(), 4, Lb.data_ptr(), BIG) == GPC_ERR_ARG
+    assert lib.gpc_trsm(h, 0, 4, 1, A.data_ptr(), BIG, y.data_ptr(), 1) == GPC_ERR_ARG
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    assert lib.gpc_logdet(h, 4, A.data_ptr(), BIG, out.data_ptr()) == GPC_ERR_ARG
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(A).item() == 0 and int(info.item()) == 0   # nothing ran
+    assert lib.gpc_check(h) == GPC_OK
+
+
+def test_overlapping_outputs_rejected(H):
+    from paper_1907_01063_amd.gpchol import GPC_ERR_ARG
+    lib, h = H.lib, H.h
+    n = 64
+    L = torch.eye(n, dtype=torch.float64, device="cuda")
+    big = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
+    H._sync_stream()
+    # Lbar == L, and Lbar starting inside L
+    assert lib.gpc_adjoint(h, n, L.data_ptr(), n, L.data_ptr(), n) == GPC_ERR_ARG
+    assert lib.gpc_adjoint(h, n, big.data_ptr(), n, big.data_ptr() + 8 * (n * n - 1), n) == GPC_ERR_ARG
+    # B overlapping L in a solve
+    assert lib.gpc_trsm(h, 0, n, 1, L.data_ptr(), n, L.data_ptr() + 8 * n, 1) == GPC_ERR_ARG
+    # refined solution overlapping y
+    it = torch.zeros(1, dtype=torch.int32, device="cuda")
+    eta = torch.zeros(1, dtype=torch.float64, device="cuda")
+    v = torch.zeros(n, dtype=torch.float64, device="cuda")
+    assert lib.gpc_solve_refined(h, n, L.data_ptr(), n, L.data_ptr(), n, v.data_ptr(), v.data_ptr(),
+                                 it.data_ptr(), eta.data_ptr()) == GPC_ERR_ARG
+    torch.cuda.synchronize()
+    say("overlap checks ok")

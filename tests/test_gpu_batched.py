@@ -172,3 +172,45 @@ def test_batched_mixed_form():
     Ls3, Ab3, _ = run(Hm, [As[i] for i in perm], [Lbs[i] for i in perm], [SIZES[i] for i in perm])
     for pos, i in enumerate(perm):
         assert np.array_equal(Ls3[pos], Ls[i]) and np.array_equal(Ab3[pos], Abs[i])
+
+
+def test_batched_recorded_into_caller_graph():
+    """A batched call inside the caller's graph capture: refused (nothing
+    enqueued, the capture stays usable) when its plan was not prepared by the
+    same call outside the capture; recorded when it was.  The caller's graph
+    is replayed three times, with eager work and synchronisations between the
+    replays, each replay bitwise equal to the eager call."""
+    from paper_1907_01063_amd import GpcError, Handle
+    from paper_1907_01063_amd.gpchol import GPC_ERR_CAPTURE
+    Hc = Handle()
+    sizes = SIZES[:8]
+    As, Lbs = make_batch(7, sizes)
+    a, off = pack(As)
+    lb, _ = pack(Lbs)
+    a0, lb0 = torch.from_numpy(a).cuda(), torch.from_numpy(lb).cuda()
+    at, lbt = a0.clone(), lb0.clone()
+    info = torch.zeros(len(sizes), dtype=torch.int32, device="cuda")
+    Hc.factor_adjoint_batched(sizes, off, at, lbt, info)   # prepares the plan
+    ref_l, ref_a = host(at).copy(), host(lbt).copy()
+    at.copy_(a0)
+    lbt.copy_(lb0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    refused = None
+    with torch.cuda.graph(g, stream=cap):
+        try:
+            Hc.factor_adjoint_batched(sizes[:5], off[:5], at, lbt, info)   # no plan for these sizes
+        except GpcError as e:
+            refused = e.status
+        Hc.factor_adjoint_batched(sizes, off, at, lbt, info)
+    assert refused == GPC_ERR_CAPTURE
+    for rep in range(3):
+        at.copy_(a0)
+        lbt.copy_(lb0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(at), ref_l) and np.array_equal(host(lbt), ref_a), rep
+        assert int(info.max().item()) == 0
+    del g

@@ -195,12 +195,18 @@ def test_one_launch_sweep_failure_path(H):
     with pytest.raises(GpcError) as ei:
         H.set_options(test_flags=2)
     assert ei.value.status == GPC_ERR_ARG
+    from paper_1907_01063_amd.gpchol import GPC_ERR_SWEEP
+    H.check()   # no failure recorded so far
     H.set_options(test_flags=1)
     try:
         for trans in (False, True):
             z = dev(B[:, :1])
             H.trsm(Lt, z, trans=trans)
             assert np.isnan(host(z)).all()
+            with pytest.raises(GpcError) as ei:   # the failure is reported once, then cleared
+                H.check()
+            assert ei.value.status == GPC_ERR_SWEEP
+            H.check()
         Z3 = dev(B)
         H.trsm(Lt, Z3)
         assert relf(host(Z3), oracle.trsm(L0, B)) <= TOL
@@ -209,6 +215,7 @@ def test_one_launch_sweep_failure_path(H):
     z = dev(B[:, :1])
     H.trsm(Lt, z)
     assert relf(host(z), oracle.trsm(L0, B[:, :1])) <= TOL
+    H.check()
 
 
 def test_trsm_vector_and_logdet(H):
