@@ -60,6 +60,21 @@ def _load():
                                        ctypes.c_double, _dp, _i64]
         lib.orc_gp_lbar.restype = None
         lib.orc_gp_lbar.argtypes = [_i64, _dp, _i64, _dp, _dp, _dp, _i64]
+        lib.orc_trtri.restype = None
+        lib.orc_trtri.argtypes = [_i64, _dp, _i64, _dp, _i64]
+        lib.orc_trsm_adjoint.restype = None
+        lib.orc_trsm_adjoint.argtypes = [ctypes.c_int, _i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64,
+                                         _dp, _i64, _dp, _i64]
+        lib.orc_trtri_adjoint.restype = None
+        lib.orc_trtri_adjoint.argtypes = [_i64, _dp, _i64, _dp, _i64, _dp, _i64]
+        lib.orc_gemm.restype = None
+        lib.orc_gemm.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _dp, _i64, _dp, _i64,
+                                 ctypes.c_double, _dp, _i64]
+        lib.orc_multiply_transpose.restype = None
+        lib.orc_multiply_transpose.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+        lib.orc_glm_bernoulli_logit.restype = None
+        lib.orc_glm_bernoulli_logit.argtypes = [_i64, _i64, _dp, _i64, ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _i64]
         lib.orc_max_threads.restype = ctypes.c_int
         lib.orc_max_threads.argtypes = []
         lib.orc_set_threads.restype = None
@@ -168,3 +183,73 @@ def gp_mll(L: np.ndarray, y: np.ndarray):
     for v in z:          # fixed order, i increasing
         zz += float(v) * float(v)
     return -0.5 * zz - 0.5 * ld, z, alpha, ld
+
+
+def trtri(L: np.ndarray) -> np.ndarray:
+    """``L^-1`` of a lower-triangular L (lower, strict upper zero)."""
+    L = _c(L)
+    n = L.shape[0]
+    X = np.zeros((n, n))
+    _load().orc_trtri(n, _p(L), n, _p(X), n)
+    return X
+
+
+def trsm_adjoint(L: np.ndarray, C: np.ndarray, Cbar: np.ndarray, trans: bool = False):
+    """Adjoints of C = L^-1 B (or L^-T B): returns (Bbar, Lbar)."""
+    L = _c(L)
+    vec = C.ndim == 1
+    C2 = _c(C.reshape(C.shape[0], -1))
+    Cb2 = _c(Cbar.reshape(Cbar.shape[0], -1))
+    n, nrhs = C2.shape
+    Bbar = np.zeros((n, nrhs))
+    Lbar = np.zeros((n, n))
+    _load().orc_trsm_adjoint(1 if trans else 0, n, nrhs, _p(L), n, _p(C2), nrhs, _p(Cb2), nrhs,
+                             _p(Bbar), nrhs, _p(Lbar), n)
+    return (Bbar[:, 0].copy() if vec else Bbar), Lbar
+
+
+def trtri_adjoint(X: np.ndarray, Xbar: np.ndarray) -> np.ndarray:
+    """Lbar of X = L^-1 given the adjoint Xbar of its lower triangle."""
+    X = _c(X)
+    Xbar = _c(Xbar)
+    n = X.shape[0]
+    Lbar = np.zeros((n, n))
+    _load().orc_trtri_adjoint(n, _p(X), n, _p(Xbar), n, _p(Lbar), n)
+    return Lbar
+
+
+def gemm(A: np.ndarray, B: np.ndarray, ta: bool = False, tb: bool = False, beta: float = 0.0,
+         C: np.ndarray | None = None) -> np.ndarray:
+    """``op(A) op(B) + beta C``."""
+    A = _c(A)
+    B = _c(B)
+    M, K = (A.shape[1], A.shape[0]) if ta else A.shape
+    N = B.shape[0] if tb else B.shape[1]
+    out = np.zeros((M, N)) if C is None else _c(C).copy()
+    _load().orc_gemm(1 if ta else 0, 1 if tb else 0, M, N, K, _p(A), A.shape[1], _p(B), B.shape[1],
+                     float(beta), _p(out), N)
+    return out
+
+
+def multiply_transpose(A: np.ndarray) -> np.ndarray:
+    """``A A^T`` (full symmetric)."""
+    A = _c(A)
+    M, K = A.shape
+    C = np.zeros((M, M))
+    _load().orc_multiply_transpose(M, K, _p(A), K, _p(C), M)
+    return C
+
+
+def glm_bernoulli_logit(X: np.ndarray, y: np.ndarray, alpha: float, beta: np.ndarray, with_dX: bool = False):
+    """Bernoulli-logit GLM: returns (lp, dalpha, dbeta, dX or None)."""
+    X = _c(X)
+    n, k = X.shape
+    yi = np.ascontiguousarray(y, dtype=np.int32)
+    beta = _c(np.asarray(beta).reshape(k))
+    lp, da = ctypes.c_double(), ctypes.c_double()
+    db = np.zeros(k)
+    dX = np.zeros((n, k)) if with_dX else None
+    _load().orc_glm_bernoulli_logit(n, k, _p(X), k, yi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    float(alpha), _p(beta), ctypes.byref(lp), ctypes.byref(da), _p(db),
+                                    _p(dX) if with_dX else None, k)
+    return lp.value, da.value, db, dX

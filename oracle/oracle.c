@@ -348,3 +348,161 @@ void orc_gp_hypergrad_se(int64_t n, int64_t d, const double* X, double sigma2,
         for (int64_t q = 0; q < m; ++q) grad[q] += rowc[i * m + q];
     free(rowc);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Lower-triangular inverse: section 3.2 (the special case of a triangular
+ * solve whose right-hand side is the identity).  X = L^-1 is the lower
+ * triangular matrix with L X = I; column j is the forward substitution of
+ * L x = e_j:
+ *   X_ij = 0 (i < j),   X_jj = 1 / L_jj,
+ *   X_ij = -(sum_{k=j}^{i-1} L_ik X_kj) / L_ii   (i > j, k increasing).
+ * Columns are independent (parallel over j).                                 */
+void orc_trtri(int64_t n, const double* L, int64_t ldl, double* X, int64_t ldx)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < j; ++i) AT(X, ldx, i, j) = 0.0;
+        AT(X, ldx, j, j) = 1.0 / AT(L, ldl, j, j);
+        for (int64_t i = j + 1; i < n; ++i) {
+            double acc = 0.0;
+            for (int64_t k = j; k < i; ++k)
+                acc += AT(L, ldl, i, k) * AT(X, ldx, k, j);
+            AT(X, ldx, i, j) = -acc / AT(L, ldl, i, i);
+        }
+    }
+}
+
+/* Reverse mode of the triangular solve: section 3.2.  For C = L^-1 B
+ * (trans 0) the adjoints are Bbar = L^-T Cbar and Lbar = -tril(Bbar C^T);
+ * for C = L^-T B (trans 1) they are Bbar = L^-1 Cbar and
+ * Lbar = -tril(C Bbar^T).  (From dC = -L^-1 dL C, resp. dC = -L^-T dL^T C:
+ * <Cbar, dC> = -<L^-T Cbar C^T, dL>, resp. -<C (L^-1 Cbar)^T, dL>, and only
+ * the lower triangle of L is a variable.)  C, Cbar, Bbar: n x nrhs; Bbar is
+ * formed by the substitutions of orc_trsm; Lbar is n x n, lower, with
+ *   Lbar_ij = -sum_c Bbar_ic C_jc   (trans 0)   or   -sum_c C_ic Bbar_jc   (trans 1)
+ * for i >= j (c increasing) and 0 above the diagonal.                          */
+void orc_trsm_adjoint(int trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
+                      const double* C, int64_t ldc, const double* Cbar, int64_t ldcb,
+                      double* Bbar, int64_t ldbb, double* Lbar, int64_t ldlb)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t c = 0; c < nrhs; ++c) AT(Bbar, ldbb, i, c) = AT(Cbar, ldcb, i, c);
+    orc_trsm(trans ? 0 : 1, n, nrhs, L, ldl, Bbar, ldbb);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            if (j <= i)
+                for (int64_t c = 0; c < nrhs; ++c)
+                    acc += trans ? AT(C, ldc, i, c) * AT(Bbar, ldbb, j, c)
+                                 : AT(Bbar, ldbb, i, c) * AT(C, ldc, j, c);
+            AT(Lbar, ldlb, i, j) = j <= i ? -acc : 0.0;
+        }
+}
+
+/* Reverse mode of the lower-triangular inverse X = L^-1 (section 3.2): from
+ * dX = -X dL X, <Xbar, dX> = -<X^T Xbar X^T, dL>, so with the adjoint of the
+ * lower triangle of X (its strict upper part is not a variable and is
+ * ignored),  Lbar = -tril(X^T tril(Xbar) X^T):
+ *   T_kj    = sum_{l} tril(Xbar)_kl X_jl          (l increasing)
+ *   Lbar_ij = -sum_k X_ki T_kj   for i >= j       (k increasing), 0 above.     */
+void orc_trtri_adjoint(int64_t n, const double* X, int64_t ldx, const double* Xbar, int64_t ldxb,
+                       double* Lbar, int64_t ldlb)
+{
+    double* T = (double*)malloc(sizeof(double) * (size_t)(n * n + 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k)
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int64_t l = 0; l <= k; ++l)
+                acc += AT(Xbar, ldxb, k, l) * AT(X, ldx, j, l);
+            T[k * n + j] = acc;
+        }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            if (j <= i)
+                for (int64_t k = 0; k < n; ++k)
+                    acc += AT(X, ldx, k, i) * T[k * n + j];
+            AT(Lbar, ldlb, i, j) = j <= i ? -acc : 0.0;
+        }
+    free(T);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Matrix product: section 3.1.  C = op(A) op(B) + beta C with op(A) M x K
+ * (A, or A^T when ta) and op(B) K x N (B, or B^T when tb):
+ *   C_ij = beta C_ij + sum_{k} op(A)_ik op(B)_kj   (k increasing).            */
+void orc_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+              const double* B, int64_t ldb, double beta, double* C, int64_t ldc)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < K; ++k)
+                acc += (ta ? AT(A, lda, k, i) : AT(A, lda, i, k)) * (tb ? AT(B, ldb, j, k) : AT(B, ldb, k, j));
+            AT(C, ldc, i, j) = (beta == 0.0 ? 0.0 : beta * AT(C, ldc, i, j)) + acc;
+        }
+}
+
+/* The special case C = A A^T of section 3.1 (multiply_transpose): A is M x K,
+ * C the full symmetric M x M product, C_ij = C_ji = sum_k A_ik A_jk.          */
+void orc_multiply_transpose(int64_t M, int64_t K, const double* A, int64_t lda, double* C, int64_t ldc)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < K; ++k)
+                acc += AT(A, lda, i, k) * AT(A, lda, j, k);
+            AT(C, ldc, i, j) = acc;
+            AT(C, ldc, j, i) = acc;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bernoulli-logit GLM log-likelihood and its gradient: section 3.4 (the
+ * likelihood of the logistic regression example, section 4.1):
+ *   mu_i = alpha + sum_j X_ij beta_j                       (j increasing)
+ *   lp   = sum_i [ y_i log s(mu_i) + (1 - y_i) log(1 - s(mu_i)) ],
+ * with s the logistic function, log s(t) = -softplus(-t),
+ * log(1 - s(t)) = -softplus(t), softplus(t) = max(t, 0) + log1p(exp(-|t|));
+ *   d_i = y_i - s(mu_i)                (dlp / dmu_i)
+ *   dalpha = sum_i d_i,   dbeta_j = sum_i X_ij d_i,   dX_ij = d_i beta_j.
+ * Sums over i run in increasing i.  dX may be NULL.  y holds 0/1 integers.  */
+static double orc_softplus(double t) { return (t > 0.0 ? t : 0.0) + log1p(exp(-fabs(t))); }
+
+void orc_glm_bernoulli_logit(int64_t n, int64_t k, const double* X, int64_t ldx, const int32_t* y,
+                             double alpha, const double* beta, double* lp, double* dalpha,
+                             double* dbeta, double* dX, int64_t lddx)
+{
+    double* d = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+    double* lpi = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double mu = alpha;
+        for (int64_t j = 0; j < k; ++j) mu += AT(X, ldx, i, j) * beta[j];
+        const double yi = (double)y[i];
+        lpi[i] = -yi * orc_softplus(-mu) - (1.0 - yi) * orc_softplus(mu);
+        d[i] = yi - 1.0 / (1.0 + exp(-mu));
+        if (dX)
+            for (int64_t j = 0; j < k; ++j) AT(dX, lddx, i, j) = d[i] * beta[j];
+    }
+    double s = 0.0, sa = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        s += lpi[i];
+        sa += d[i];
+    }
+    *lp = s;
+    *dalpha = sa;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < k; ++j) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) acc += AT(X, ldx, i, j) * d[i];
+        dbeta[j] = acc;
+    }
+    free(lpi);
+    free(d);
+}

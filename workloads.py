@@ -22,6 +22,14 @@ Workloads (n is the matrix order):
 * ``c5``: n = 30000 GP marginal-likelihood inputs, x ~ N(0, I_8), y ~ N(0, I),
   SE-ARD base hyperparameters (1, ell_d = 2, 0.1) and 100 jittered copies
   theta_e = theta_base * exp(0.1 xi_e), xi_e ~ N(0, I_10).
+* ``tri``: a lower-triangular factor with diagonal |N(0,1)| + 1 and N(0, 1/n)
+  entries below it, a right-hand side block B ~ N(0,1) and adjoint seeds
+  ~ N(0,1) (triangular solve and inverse, and their reverse modes).
+* ``gemm``: A, B and an output adjoint ~ N(0,1) of given shapes (matrix
+  products and their reverse mode).
+* ``glm``: the logistic-regression data of section 4.1: X ~ N(0,1) of n x k,
+  mu_i = 3 X_i1 - 2 X_i2 + 1, y_i ~ Bernoulli(1 / (1 + exp(-mu_i))); the
+  likelihood is evaluated at (alpha, beta) = (1, 3, -2, 0, ..., 0) + 0.1 xi.
 
 Lbar, the adjoint fed to the reverse pass, has N(0, 1) entries on and below the
 diagonal and zeros above it.
@@ -32,7 +40,8 @@ import math
 
 import numpy as np
 
-SEEDS = {"toeplitz": 1000, "c1": 1001, "c2": 1002, "c3": 1003, "c4": 1004, "c5": 1005}
+SEEDS = {"toeplitz": 1000, "c1": 1001, "c2": 1002, "c3": 1003, "c4": 1004, "c5": 1005,
+         "tri": 1006, "gemm": 1007, "glm": 1008}
 
 _ROWS = 1024   # rows per chunk when assembling large covariances
 
@@ -183,6 +192,37 @@ def spd_from_factor(rng: np.random.Generator, n: int):
     L0 = np.tril(rng.standard_normal((n, n)), -1) / math.sqrt(max(n, 1))
     L0[np.diag_indices(n)] = np.abs(rng.standard_normal(n)) + 1.0
     return L0 @ L0.T, L0
+
+
+def tri(n: int, nrhs: int = 1, seed: int = SEEDS["tri"]) -> dict:
+    rng = np.random.default_rng(seed)
+    L = np.tril(rng.standard_normal((n, n)), -1) / math.sqrt(max(n, 1))
+    L[np.diag_indices(n)] = np.abs(rng.standard_normal(n)) + 1.0
+    B = rng.standard_normal((n, nrhs))
+    Cbar = rng.standard_normal((n, nrhs))
+    Xbar = lower_normal(rng, n)
+    return {"name": f"tri-n{n}-r{nrhs}", "L": L, "B": B, "Cbar": Cbar, "Xbar": Xbar}
+
+
+def gemm_case(M: int, N: int, K: int, seed: int = SEEDS["gemm"]) -> dict:
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    Cbar = rng.standard_normal((M, N))
+    return {"name": f"gemm-{M}x{N}x{K}", "A": A, "B": B, "Cbar": Cbar}
+
+
+def glm(n: int, k: int, seed: int = SEEDS["glm"]) -> dict:
+    """Logistic-regression data (section 4.1) and one parameter point."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, k))
+    mu = 3.0 * X[:, 0] - 2.0 * X[:, 1] + 1.0 if k >= 2 else X[:, 0] + 1.0
+    y = (rng.random(n) < 1.0 / (1.0 + np.exp(-mu))).astype(np.int32)
+    theta = np.zeros(k + 1)
+    theta[0] = 1.0
+    theta[1:3] = (3.0, -2.0)[:min(2, k)]
+    theta += 0.1 * rng.standard_normal(k + 1)
+    return {"name": f"glm-n{n}-k{k}", "X": X, "y": y, "alpha": float(theta[0]), "beta": theta[1:]}
 
 
 def flops_factor(n: int) -> float:
