@@ -75,6 +75,8 @@ typedef struct {
     int32_t test_flags;    /* 0; 1 = start every one-launch solve sweep (a single right-hand
                               side) with its error flag raised: its waits return at once and
                               its solution entries are NaN, which tests the failure path */
+    int32_t gemm_max_splits; /* largest split-K count of gpc_gemm (gpchol_ops.h); 0 = 32
+                                (default), 1 = never split */
 } gpc_options;
 
 typedef struct gpc_handle gpc_handle;
@@ -249,7 +251,8 @@ typedef enum {
     GPC_K_REDUCE = 9,           /* fixed-order sum of split-K slices into Rbar */
     GPC_K_BATCHED = 10,         /* one persistent batched launch (graph replay) */
     GPC_K_TRAILING_NARROW = 11, /* trailing update of the next block's columns only */
-    GPC_K_COUNT = 12
+    GPC_K_OPS = 12,             /* the entry points of gpchol_ops.h, one record per call */
+    GPC_K_COUNT = 13
 } gpc_kernel_class;
 
 /* Launch trace, for measurement: while enabled, every launch of the classes

@@ -40,6 +40,7 @@ struct BatchPlan {
 struct gpc_handle {
     int device = 0;
     int cus = 256;
+    int32_t last_splits = 1;             // split count of the last gpc_gemm
     int tune_block[kTuneBuckets] = {64, 64, 64, 64, 64};
     bool tuned = false;
     hipStream_t cap_stream = nullptr;    // private stream used only to capture graphs
@@ -467,6 +468,7 @@ gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
     if (o->refine_maxit < 0 || !(o->refine_tol > 0.0)) return GPC_ERR_ARG;
     if (o->mixed_fallback != 0 && o->mixed_fallback != 1) return GPC_ERR_ARG;
     if (o->test_flags != 0 && o->test_flags != 1) return GPC_ERR_ARG;
+    if (o->gemm_max_splits < 0 || o->gemm_max_splits > kGemmMaxSplits) return GPC_ERR_ARG;
     h->opt = *o;
     return GPC_OK;
 }
@@ -1242,6 +1244,207 @@ gpc_status gpc_get_tuning(const gpc_handle* h, int32_t* blocks_out, int32_t* tun
     if (!h || !blocks_out || !tuned) return GPC_ERR_ARG;
     for (int b = 0; b < kTuneBuckets; ++b) blocks_out[b] = h->tune_block[b];
     *tuned = h->tuned ? 1 : 0;
+    return GPC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Operations beside the Cholesky path (include/gpchol_ops.h): the triangular
+// inverse and the reverse modes of the solve and the inverse (section 3.2),
+// products and their reverse mode (section 3.1), the Bernoulli-logit GLM
+// (section 3.4).
+#include "gpchol_ops.h"
+
+namespace {
+
+bool trans_ok(int32_t t) { return t == 0 || t == 1; }
+
+}  // namespace
+
+extern "C" {
+
+gpc_status gpc_trtri(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* X, int64_t ldx)
+{
+    if (!h || n < 0 || !ld_ok(n, ldl) || !ld_ok(n, ldx) || (n > 0 && (!L || !X))) return GPC_ERR_ARG;
+    if (overlap(L, n, n, ldl, X, n, n, ldx)) return GPC_ERR_ARG;
+    if (n == 0) return GPC_OK;
+    const double dn = (double)n;
+    Traced tr(h, GPC_K_OPS, dn * dn * dn / 3.0, 16.0 * dn * dn);
+    GPC_HIP(h, trtri_full(h->stream, n, L, ldl, X, ldx));
+    return GPC_OK;
+}
+
+gpc_status gpc_trtri_adjoint(gpc_handle* h, int64_t n, const double* X, int64_t ldx, const double* Xbar,
+                             int64_t ldxb, double* Lbar, int64_t ldlb)
+{
+    if (!h || n < 0 || !ld_ok(n, ldx) || !ld_ok(n, ldxb) || !ld_ok(n, ldlb) || (n > 0 && (!X || !Xbar || !Lbar)))
+        return GPC_ERR_ARG;
+    if (overlap(Lbar, n, n, ldlb, X, n, n, ldx) || overlap(Lbar, n, n, ldlb, Xbar, n, n, ldxb)) return GPC_ERR_ARG;
+    if (n == 0) return GPC_OK;
+    gpc_status st = ensure_ws(h, sizeof(double) * (size_t)n * (size_t)n);
+    if (st != GPC_OK) return st;
+    double* Pt = (double*)h->ws;   // P^T = tril(Xbar)^T X, n x n
+    hipStream_t s = h->stream;
+    const double dn = (double)n;
+    Traced tr(h, GPC_K_OPS, 2.0 * dn * dn * dn, 8.0 * 5.0 * dn * dn);
+    GemmArgs g1{};
+    g1.M = n; g1.N = n; g1.K = n;
+    g1.A = Xbar; g1.lda = ldxb; g1.a_lower = 1;   // read k-major: Xbar^T, its strict upper part masked
+    g1.B = X; g1.ldb = ldx;
+    g1.C = Pt; g1.ldc = n;
+    g1.kchunk = n;
+    GPC_HIP(h, gemm_f64(s, TILE_128, true, false, EPI_STORE, false, g1, 1));
+    GemmArgs g2{};                                  // Lbar = -tril(P X^T), lower tiles
+    g2.M = n; g2.N = n; g2.K = n;
+    g2.A = Pt; g2.lda = n;                          // read k-major: (P^T)^T = P
+    g2.B = X; g2.ldb = ldx;                         // read n-major: X^T
+    g2.C = Lbar; g2.ldc = ldlb;
+    g2.kchunk = n;
+    g2.negate = 1;
+    GPC_HIP(h, gemm_f64(s, TILE_128, true, true, EPI_STORE, true, g2, 1));
+    GPC_HIP(h, zero_strict_upper(s, n, Lbar, ldlb));
+    return GPC_OK;
+}
+
+gpc_status gpc_trsm_adjoint(gpc_handle* h, int32_t trans, int64_t n, int64_t nrhs, const double* L, int64_t ldl,
+                            const double* C, int64_t ldc, double* Cbar, int64_t ldcb, double* Lbar, int64_t ldlb)
+{
+    if (!h || !trans_ok(trans) || n < 0 || nrhs < 0 || !ld_ok(n, ldl) || !ld_ok(nrhs, ldc) || !ld_ok(nrhs, ldcb) ||
+        !ld_ok(n, ldlb) || (n > 0 && (!L || !Lbar)) || (n > 0 && nrhs > 0 && (!C || !Cbar)))
+        return GPC_ERR_ARG;
+    if (overlap(Cbar, n, nrhs, ldcb, L, n, n, ldl) || overlap(Cbar, n, nrhs, ldcb, C, n, nrhs, ldc) ||
+        overlap(Lbar, n, n, ldlb, L, n, n, ldl) || overlap(Lbar, n, n, ldlb, C, n, nrhs, ldc) ||
+        overlap(Lbar, n, n, ldlb, Cbar, n, nrhs, ldcb))
+        return GPC_ERR_ARG;
+    if (n == 0) return GPC_OK;
+    hipStream_t s = h->stream;
+    // Bbar = L^-T Cbar (trans 0) or L^-1 Cbar (trans 1), in place
+    gpc_status st = gpc_trsm(h, trans ? GPC_NOTRANS : GPC_TRANS, n, nrhs, L, ldl, Cbar, ldcb);
+    if (st != GPC_OK) return st;
+    const double dn = (double)n, dr = (double)nrhs;
+    Traced tr(h, GPC_K_OPS, dn * (dn + 1.0) * dr, 8.0 * (2.0 * dn * dr + dn * (dn + 1.0) / 2.0));
+    // Lbar = -tril(Bbar C^T) (trans 0) or -tril(C Bbar^T) (trans 1): lower tiles
+    GemmArgs g{};
+    g.M = n; g.N = n; g.K = nrhs;
+    g.A = trans ? C : Cbar; g.lda = trans ? ldc : ldcb;
+    g.B = trans ? Cbar : C; g.ldb = trans ? ldcb : ldc;
+    g.C = Lbar; g.ldc = ldlb;
+    g.kchunk = std::max<int64_t>(1, nrhs);
+    g.negate = nrhs > 0;                            // no right-hand side: Lbar = +0
+    GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_STORE, true, g, 1));
+    GPC_HIP(h, zero_strict_upper(s, n, Lbar, ldlb));
+    return GPC_OK;
+}
+
+gpc_status gpc_gemm(gpc_handle* h, int32_t ta, int32_t tb, int64_t M, int64_t N, int64_t K, const double* A,
+                    int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc)
+{
+    if (!h || !trans_ok(ta) || !trans_ok(tb) || M < 0 || N < 0 || K < 0 || !(beta == 0.0 || beta == 1.0))
+        return GPC_ERR_ARG;
+    if (!ld_ok(ta ? M : K, lda) || !ld_ok(tb ? K : N, ldb) || !ld_ok(N, ldc)) return GPC_ERR_ARG;
+    if (M > 0 && N > 0 && (!C || (K > 0 && (!A || !B)))) return GPC_ERR_ARG;
+    if (overlap(C, M, N, ldc, A, ta ? K : M, ta ? M : K, lda) || overlap(C, M, N, ldc, B, tb ? N : K, tb ? K : N, ldb))
+        return GPC_ERR_ARG;
+    if (M == 0 || N == 0) return GPC_OK;
+    const int msp = h->opt.gemm_max_splits > 0 ? h->opt.gemm_max_splits : kGemmMaxSplits;
+    const int64_t wsd = gemm_general_workspace(M, N, K, h->cus, msp);
+    gpc_status st = ensure_ws(h, sizeof(double) * (size_t)std::max<int64_t>(wsd, 1));
+    if (st != GPC_OK) return st;
+    const double dM = (double)M, dN = (double)N, dK = (double)K;
+    Traced tr(h, GPC_K_OPS, 2.0 * dM * dN * dK, 8.0 * (dM * dK + dK * dN + (beta == 0.0 ? 1.0 : 2.0) * dM * dN));
+    int sp = 1;
+    GPC_HIP(h, gemm_general(h->stream, ta != 0, tb != 0, M, N, K, A, lda, B, ldb, beta, C, ldc, (double*)h->ws,
+                            h->cus, msp, &sp));
+    h->last_splits = sp;
+    return GPC_OK;
+}
+
+gpc_status gpc_gemm_adjoint(gpc_handle* h, int32_t ta, int32_t tb, int64_t M, int64_t N, int64_t K, const double* A,
+                            int64_t lda, const double* B, int64_t ldb, const double* Cbar, int64_t ldcb, double beta,
+                            double* Abar, int64_t ldab, double* Bbar, int64_t ldbb)
+{
+    if (!h || !trans_ok(ta) || !trans_ok(tb) || M < 0 || N < 0 || K < 0 || !(beta == 0.0 || beta == 1.0))
+        return GPC_ERR_ARG;
+    const int64_t ar = ta ? K : M, ac = ta ? M : K;   // stored shape of A
+    const int64_t br = tb ? N : K, bc = tb ? K : N;   // stored shape of B
+    if (!ld_ok(ac, lda) || !ld_ok(bc, ldb) || !ld_ok(N, ldcb)) return GPC_ERR_ARG;
+    if (Abar && !ld_ok(ac, ldab)) return GPC_ERR_ARG;
+    if (Bbar && !ld_ok(bc, ldbb)) return GPC_ERR_ARG;
+    if (overlap(Abar, ar, ac, ldab, Bbar, br, bc, ldbb) || overlap(Abar, ar, ac, ldab, Cbar, M, N, ldcb) ||
+        overlap(Bbar, br, bc, ldbb, Cbar, M, N, ldcb) || overlap(Abar, ar, ac, ldab, B, br, bc, ldb) ||
+        overlap(Bbar, br, bc, ldbb, A, ar, ac, lda))
+        return GPC_ERR_ARG;
+    // op(A) = A:   Abar  = Cbar op(B)^T           op(A) = A^T: Abar = op(B) Cbar^T
+    // op(B) = B:   Bbar  = op(A)^T Cbar           op(B) = B^T: Bbar = Cbar^T op(A)
+    if (Abar) {
+        gpc_status st = ta ? gpc_gemm(h, tb, 1, K, M, N, B, ldb, Cbar, ldcb, beta, Abar, ldab)
+                           : gpc_gemm(h, 0, tb ? 0 : 1, M, K, N, Cbar, ldcb, B, ldb, beta, Abar, ldab);
+        if (st != GPC_OK) return st;
+    }
+    if (Bbar) {
+        gpc_status st = tb ? gpc_gemm(h, 1, ta, N, K, M, Cbar, ldcb, A, lda, beta, Bbar, ldbb)
+                           : gpc_gemm(h, ta ? 0 : 1, 0, K, N, M, A, lda, Cbar, ldcb, beta, Bbar, ldbb);
+        if (st != GPC_OK) return st;
+    }
+    return GPC_OK;
+}
+
+gpc_status gpc_multiply_transpose(gpc_handle* h, int64_t M, int64_t K, const double* A, int64_t lda, double* C,
+                                  int64_t ldc)
+{
+    if (!h || M < 0 || K < 0 || !ld_ok(K, lda) || !ld_ok(M, ldc) || (M > 0 && (!C || (K > 0 && !A))))
+        return GPC_ERR_ARG;
+    if (overlap(C, M, M, ldc, A, M, K, lda)) return GPC_ERR_ARG;
+    if (M == 0) return GPC_OK;
+    const double dM = (double)M, dK = (double)K;
+    Traced tr(h, GPC_K_OPS, dM * (dM + 1.0) * dK, 8.0 * (dM * dK + dM * dM));
+    GemmArgs g{};
+    g.M = M; g.N = M; g.K = K;
+    g.A = A; g.lda = lda;
+    g.B = A; g.ldb = lda;
+    g.C = C; g.ldc = ldc;
+    g.kchunk = K > 0 ? K : 1;
+    GPC_HIP(h, gemm_f64(h->stream, TILE_128, false, true, EPI_SYMLOW, true, g, 1));
+    return GPC_OK;
+}
+
+gpc_status gpc_multiply_transpose_adjoint(gpc_handle* h, int64_t M, int64_t K, const double* A, int64_t lda,
+                                          const double* Cbar, int64_t ldcb, double beta, double* Abar, int64_t ldab)
+{
+    // C = A A^T:  Abar = (Cbar + Cbar^T) A + beta Abar
+    if (!h || M < 0 || K < 0 || !(beta == 0.0 || beta == 1.0) || !ld_ok(K, lda) || !ld_ok(M, ldcb) ||
+        !ld_ok(K, ldab) || (M > 0 && K > 0 && (!A || !Cbar || !Abar)))
+        return GPC_ERR_ARG;
+    if (overlap(Abar, M, K, ldab, A, M, K, lda) || overlap(Abar, M, K, ldab, Cbar, M, M, ldcb)) return GPC_ERR_ARG;
+    if (M == 0 || K == 0) return GPC_OK;
+    gpc_status st = gpc_gemm(h, 0, 0, M, K, M, Cbar, ldcb, A, lda, beta, Abar, ldab);
+    if (st != GPC_OK) return st;
+    return gpc_gemm(h, 1, 0, M, K, M, Cbar, ldcb, A, lda, 1.0, Abar, ldab);
+}
+
+gpc_status gpc_glm_bernoulli_logit(gpc_handle* h, int64_t n, int64_t k, const double* X, int64_t ldx,
+                                   const int32_t* y, const double* alpha, const double* beta, double* lp,
+                                   double* dalpha, double* dbeta, double* dX, int64_t lddx)
+{
+    if (!h || n < 0 || k < 0 || !ld_ok(k, ldx) || !alpha || !lp || !dalpha || (k > 0 && (!beta || !dbeta)) ||
+        (n > 0 && (!y || (k > 0 && !X))) || (dX && !ld_ok(k, lddx)))
+        return GPC_ERR_ARG;
+    if (dX && (overlap(dX, n, k, lddx, X, n, k, ldx)))
+        return GPC_ERR_ARG;
+    gpc_status st = ensure_ws(h, sizeof(double) * (size_t)glm_workspace(n, k));
+    if (st != GPC_OK) return st;
+    const double dn = (double)n, dk = (double)k;
+    Traced tr(h, GPC_K_OPS, 4.0 * dn * dk, 8.0 * dn * dk * (dX ? 2.0 : 1.0) + 4.0 * dn);
+    GPC_HIP(h, glm_bernoulli_logit(h->stream, n, k, X, ldx, y, alpha, beta, lp, dalpha, dbeta, dX, lddx,
+                                   (double*)h->ws));
+    return GPC_OK;
+}
+
+gpc_status gpc_get_last_splits(const gpc_handle* h, int32_t* splits)
+{
+    if (!h || !splits) return GPC_ERR_ARG;
+    *splits = h->last_splits;
     return GPC_OK;
 }
 

@@ -101,6 +101,21 @@ hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, b
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_SYMLOW, false)
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, false, false, EPI_STORE, false)
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_PHI, false)
+    // general products op(A) op(B) (section 3.1) and their split-K slices;
+    // lower-tile products for the reverse modes of the triangular solve and
+    // inverse, and C = A A^T mirrored over the diagonal
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, false, EPI_STORE, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, true, EPI_STORE, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, false, EPI_ADD, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_ADD, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, false, EPI_ADD, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, true, EPI_ADD, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, false, EPI_PARTIAL, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_PARTIAL, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, true, EPI_PARTIAL, false)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_STORE, true)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, true, EPI_STORE, true)
+    GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, true, EPI_SYMLOW, true)
     return hipErrorInvalidValue;
 }
 

@@ -189,19 +189,21 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
 #pragma unroll
         for (int p = 0; p < LB; ++p) rb[p] = (TI)buffer_ld<TG>(rs, o[p]);
     };
-    // FP64 subtract: the accumulators start at C and the MFMAs are fed -A,
-    // so they form C - A B directly and the epilogue only writes.  The C
-    // loads are issued right after the first operand chunk's, so their
-    // latency overlaps it instead of following the last MFMA.
-    constexpr bool kFold = EPI == EPI_SUB && sizeof(TI) == 8;
+    // FP64 subtract (add): the accumulators start at C and the MFMAs are fed
+    // -A (A), so they form C - A B (C + A B) directly and the epilogue only
+    // writes.  The C loads are issued right after the first operand chunk's,
+    // so their latency overlaps it instead of following the last MFMA.
+    constexpr bool kAcc = EPI == EPI_SUB || EPI == EPI_ADD;
+    constexpr bool kFold = kAcc && sizeof(TI) == 8;
+    constexpr bool kNegA = kFold && EPI == EPI_SUB;
     // FP32 subtract from FP64 C, small tiles: C is read into FP64 registers at
     // the same point (there is room for them in a 64 x 64 tile) and the
     // epilogue writes C - A B without a read of its own
-    constexpr bool kPre = EPI == EPI_SUB && sizeof(TI) == 4 && FM * FN <= 4;
+    constexpr bool kPre = kAcc && sizeof(TI) == 4 && FM * FN <= 4;
     // FP32 subtract, larger tiles: the same FP64 copy of C is read just
     // before the last k-chunk, when the staging registers are free, so its
     // latency overlaps that chunk's MFMAs
-    constexpr bool kLate = EPI == EPI_SUB && sizeof(TI) == 4 && !kPre;
+    constexpr bool kLate = kAcc && sizeof(TI) == 4 && !kPre;
     constexpr bool kC = kPre || kLate;
     typedef typename Mfma<TI>::acc_t acc_t;
     acc_t acc[FM][FN];
@@ -228,7 +230,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
     auto store = [&](int buf) {
 #pragma unroll
         for (int p = 0; p < LA; ++p) {
-            const TI v = kFold ? -ra[p] : ra[p];
+            const TI v = kNegA ? -ra[p] : ra[p];
             if (AKM) sA(buf, kA + p * ASTEP)[mA] = v;
             else sA(buf, kA)[mA + p * ASTEP] = v;
         }
@@ -281,7 +283,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                 const int r = wm * WTM + i * 16 + lc;
                 if (dir) {
                     const TI x = frag(bufA, k, r, AKM && sizeof(TI) == 8, !AKM);
-                    a[i] = kFold ? -x : x;
+                    a[i] = kNegA ? -x : x;
                 } else {
                     a[i] = sA(cur, k)[r];
                 }
@@ -438,8 +440,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
                     if (kFold) g.C[row * g.ldc + col] = v;
                     else if (kC) g.C[row * g.ldc + col] = cpre[kC ? i : 0][kC ? j : 0][r] - v;
                     else g.C[row * g.ldc + col] -= v;
+                } else if (EPI == EPI_ADD) {
+                    if (kFold) g.C[row * g.ldc + col] = v;
+                    else if (kC) g.C[row * g.ldc + col] = cpre[kC ? i : 0][kC ? j : 0][r] + v;
+                    else g.C[row * g.ldc + col] += v;
                 } else if (EPI == EPI_STORE) {
-                    g.C[row * g.ldc + col] = v;
+                    g.C[row * g.ldc + col] = g.negate ? -v : v;
                     if (g.Cf) g.Cf[row * g.ldcf + col] = (float)v;
                 } else if (EPI == EPI_PARTIAL) {
                     g.C[z * g.pstride + row * g.ldc + col] = v;

@@ -24,7 +24,8 @@ enum Epi : int {
     EPI_STORE = 1,    // C[m][n]  = acc   (C may alias A when one tile spans all N)
     EPI_PARTIAL = 2,  // C[z*pstride + m*ldc + n] = acc   (split-K slice z)
     EPI_SYMLOW = 3,   // for m >= n: C[m][n] = C[n][m] = acc   (symmetric from lower)
-    EPI_PHI = 4       // C[m][n] = acc (full);  C2[m][n] = m>n ? acc : m==n ? acc/2 : 0
+    EPI_PHI = 4,      // C[m][n] = acc (full);  C2[m][n] = m>n ? acc : m==n ? acc/2 : 0
+    EPI_ADD = 5       // C[m][n] += acc
 };
 
 struct GemmArgs {
@@ -40,6 +41,7 @@ struct GemmArgs {
     float* Cf; int64_t ldcf;  // EPI_STORE / EPI_PHI: optional FP32 copy of the stored C (nullptr = none)
     int32_t c_lower;          // nonzero: never write C elements with col > row (C-local indices)
     int64_t bsA, bsB, bsC;    // batch strides (elements) applied per blockIdx.y
+    int32_t negate;           // EPI_STORE: store -acc
 };
 
 enum TileCfg : int { TILE_128 = 0, TILE_64 = 1 };
@@ -130,6 +132,35 @@ hipError_t refine_eta(hipStream_t s, int64_t n, const double* r, const double* x
 hipError_t vec_axpy(hipStream_t s, int64_t n, const double* d, double* x);
 hipError_t vec_copy(hipStream_t s, int64_t n, const double* a, double* b);
 hipError_t vec_zero(hipStream_t s, int64_t n, double* a);
+
+// ---- operations beside the Cholesky path (ops.hip) ---------------------------
+// X = L^-1 (lower, strict upper zeroed; X must not overlap L): inverses of the
+// 128-blocks, then the divide-and-conquer levels C3 = -C2 A3 C1 of section 3.2.
+hipError_t trtri_full(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* X, int64_t ldx);
+// Split-K plan of a product of `tiles` 128 x 128 output tiles with inner
+// dimension K on `slots` co-resident workgroups: splits (<= max_splits) and
+// the chunk of k per split (a multiple of 32).
+void plan_split_k(int64_t tiles, int64_t K, int max_splits, int64_t slots, int* splits, int64_t* chunk);
+// C = op(A) op(B) + beta C (beta 0 or 1; op = transpose when ta / tb):
+// 128 x 128 MFMA tiles, split along k when the plan says so (partial slices
+// in ws, gemm_general_workspace doubles, then a fixed-order sum).
+constexpr int kGemmMaxSplits = 32;
+int64_t gemm_general_workspace(int64_t M, int64_t N, int64_t K, int cus, int max_splits);
+hipError_t gemm_general(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, const double* A,
+                        int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* ws,
+                        int cus, int max_splits, int* splits_out);
+// C[m][n] = beta C[m][n] + sum_{z<S} P[z*pstride + m*N + n] (z increasing), beta 0 or 1.
+hipError_t reduce_store(hipStream_t s, int64_t M, int64_t N, const double* P, int S, int64_t pstride, double beta,
+                        double* C, int64_t ldc);
+// Bernoulli-logit GLM (y 0/1): lp, dalpha, dbeta (device) and dX (optional);
+// ws: glm_workspace(n, k) doubles.  Rows are fused in one pass for
+// k <= kGlmFusedMaxK, two passes beyond.
+constexpr int64_t kGlmFusedMaxK = 2048;
+int64_t glm_groups(int64_t n, int64_t k);
+int64_t glm_workspace(int64_t n, int64_t k);
+hipError_t glm_bernoulli_logit(hipStream_t s, int64_t n, int64_t k, const double* X, int64_t ldx, const int32_t* y,
+                               const double* alpha, const double* beta, double* lp, double* dalpha, double* dbeta,
+                               double* dX, int64_t lddx, double* ws);
 
 // ---- batched persistent path (batched.hip) ----------------------------------
 struct BatchTask {

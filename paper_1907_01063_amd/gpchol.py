@@ -36,7 +36,7 @@ EXPORTS = (
 # Kernel classes of the launch trace (gpc_kernel_class).
 KERNEL_CLASSES = ("diag_factor", "panel_solve", "trailing_update", "diag_inverse", "adj_panel_solve",
                   "adj_left_update", "adj_diag_product", "adj_diag_block", "adj_row_update", "reduce",
-                  "batched", "trailing_narrow")
+                  "batched", "trailing_narrow", "ops")
 
 
 class GpcError(RuntimeError):
@@ -49,7 +49,7 @@ class gpc_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("lookahead", ctypes.c_int32), ("refine_maxit", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("mixed_fallback", ctypes.c_int32),
-                ("test_flags", ctypes.c_int32)]
+                ("test_flags", ctypes.c_int32), ("gemm_max_splits", ctypes.c_int32)]
 
 
 _i64, _i32, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p

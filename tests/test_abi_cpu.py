@@ -6,23 +6,29 @@ import re
 
 import pytest
 
-from paper_1907_01063_amd import gpchol
+from paper_1907_01063_amd import gpchol, ops
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gpchol.h")
+HEADERS = {"gpchol.h": gpchol.EXPORTS, "gpchol_ops.h": ops.OPS_EXPORTS}
 
 
-def declared_symbols():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(gpc_[a-z0-9_]+)\s*\(", txt)))
+def declared_symbols(header=None):
+    names = [header] if header else sorted(HEADERS)
+    syms = set()
+    for h in names:
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        syms |= set(re.findall(r"\b(gpc_[a-z0-9_]+)\s*\(", txt))
+    return sorted(syms)
 
 
 def test_header_declares_expected_entry_points():
-    syms = declared_symbols()
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == sorted(HEADERS)
+    syms = declared_symbols("gpchol.h")
     for s in ("gpc_create", "gpc_factor", "gpc_adjoint", "gpc_trsm", "gpc_logdet"):
         assert s in syms
-    assert sorted(gpchol.EXPORTS) == syms
+    for h, exports in HEADERS.items():
+        assert sorted(exports) == declared_symbols(h), h
 
 
 def test_library_exports_every_declared_symbol():
@@ -43,6 +49,11 @@ def test_null_handle_and_bad_arguments_rejected():
     assert lib.gpc_set_options(None, None) == E
     assert lib.gpc_get_fallback(None, None) == E
     assert lib.gpc_check(None) == E
+    ol = ops.lib()
+    assert ol.gpc_trtri(None, 4, None, 4, None, 4) == E
+    assert ol.gpc_trsm_adjoint(None, 0, 4, 1, None, 4, None, 1, None, 1, None, 4) == E
+    assert ol.gpc_gemm(None, 0, 0, 4, 4, 4, None, 4, None, 4, 0.0, None, 4) == E
+    assert ol.gpc_glm_bernoulli_logit(None, 4, 2, None, 2, None, None, None, None, None, None, None, 2) == E
 
 
 def test_status_strings():
@@ -63,8 +74,9 @@ def test_create_without_device_reports_no_device():
 
 
 def test_options_struct_layout():
-    # the binding's struct mirrors gpc_options: four int32, a double, two int32
+    # the binding's struct mirrors gpc_options: four int32, a double, three int32
     o = gpchol.gpc_options()
-    assert ctypes.sizeof(o) == 32
+    assert ctypes.sizeof(o) == 40
+    assert gpchol.gpc_options.gemm_max_splits.offset == 32
     assert gpchol.gpc_options.refine_tol.offset == 16
     assert gpchol.gpc_options.mixed_fallback.offset == 24

@@ -12,6 +12,7 @@ import math
 import os
 
 import numpy as np
+import torch
 import pytest
 import scipy.linalg as sla
 
@@ -206,37 +207,38 @@ def test_adjoint_matches_torch_autograd():
     assert relf(oracle.potrf_adjoint(L, Lb), mapped) < 1e-11
 
 
-def _blocked_reverse(L, Lbar, b):
-    """The paper's blocked gradient (section 3.3.2), re-derived with NumPy
-    primitives: sweep the diagonal blocks from the last to the first, push the
-    block's adjoint through the panel solve, the rank-b updates and the
-    diagonal block's own factorisation, then halve the block's diagonal."""
-    n = L.shape[0]
-    G = np.tril(Lbar).astype(float).copy()
-    hi = n
-    while hi > 0:
-        lo = max(0, hi - b)
-        Dg = L[lo:hi, lo:hi]
-        Dinv = np.linalg.inv(Dg)
-        panel_bar = G[hi:, lo:hi] @ Dinv                     # adjoint of the panel numerator
-        G[hi:, lo:hi] = panel_bar
-        G[hi:, :lo] -= panel_bar @ L[lo:hi, :lo]             # through the panel's rank-b term
-        Dbar = np.tril(G[lo:hi, lo:hi] - panel_bar.T @ L[hi:, lo:hi])
-        P = np.tril(Dg.T @ Dbar)
-        S = P + np.tril(P, -1).T
-        M = Dinv.T @ S @ Dinv                                # adjoint of the Schur block
-        G[lo:hi, :lo] -= panel_bar.T @ L[hi:, :lo] + M @ L[lo:hi, :lo]
-        G[lo:hi, lo:hi] = phi(M)
-        hi = lo
-    return G
+def _chol_blocked(S, b):
+    """Right-looking blocked factor of section 3.3.1 in torch-CPU ops: factor
+    the leading diagonal block, solve the panel against it, then factor the
+    Schur complement the same way (blocks of b columns)."""
+    n = S.shape[0]
+    k = min(b, n)
+    L11 = torch.linalg.cholesky(S[:k, :k])
+    if k == n:
+        return L11
+    L21 = torch.linalg.solve_triangular(L11, S[k:, :k].T, upper=False).T
+    L22 = _chol_blocked(S[k:, k:] - L21 @ L21.T, b)
+    top = torch.cat([L11, torch.zeros(k, n - k, dtype=S.dtype)], 1)
+    return torch.cat([top, torch.cat([L21, L22], 1)], 0)
+
+
+def _blocked_forward_gradient(A, Lbar, b):
+    """A second derivation of the adjoint: torch autograd of the blocked
+    forward factor, with the symmetric input built from its independent
+    lower-triangle entries (so the gradient is taken with respect to them)."""
+    T = torch.tensor(np.tril(A), requires_grad=True)
+    S = torch.tril(T) + torch.tril(T, -1).T
+    L = _chol_blocked(S, b)
+    (torch.tensor(np.tril(Lbar)) * L).sum().backward()
+    return np.tril(T.grad.numpy())
 
 
 @pytest.mark.parametrize("b", [1, 2, 3, 7, 64, 100])
-def test_adjoint_matches_blocked_reverse(b):
+def test_adjoint_matches_autograd_of_blocked_factor(b):
     case = W.c1(n=100)
     L, _ = oracle.potrf(case["A"])
     Lb = case["Lbar"][:100, :100]
-    assert relf(oracle.potrf_adjoint(L, Lb), _blocked_reverse(L, Lb, b)) < 1e-11
+    assert relf(oracle.potrf_adjoint(L, Lb), _blocked_forward_gradient(case["A"], Lb, b)) < 1e-11
 
 
 def test_adjoint_linear_in_lbar():
