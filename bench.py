@@ -134,6 +134,118 @@ def measured_traffic(kernel: str):
 PROGRESS = False   # --progress: one line per step (each step then waits for the GPU)
 
 
+def ops_bench(reps: int = 5):
+    """The operations beside the factor (lower-triangular inverse and the
+    reverse modes of the solve and the inverse, products and their split-K
+    form, A A^T, the Bernoulli-logit GLM), each on seeded synthetic inputs
+    of a stated shape: median of `reps` launches after one warm-up, as
+    GFLOP/s against the FP64 matrix peak (contractions) or GB/s of
+    algorithmic bytes against 8 TB/s (the GLM)."""
+    import statistics
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1907_01063_amd import Handle
+    from paper_1907_01063_amd import ops as O
+    dev = "cuda"
+    H = Handle()
+
+    def med_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+
+    out = {}
+
+    def rec(name, ms, flops=None, nbytes=None, note=""):
+        r = {"ms": round(ms, 4)}
+        if flops is not None:
+            tf = flops / (ms * 1e-3) / 1e12
+            r.update({"flops": flops, "TFLOP/s": round(tf, 2), "frac_fp64_peak": round(tf / PEAK_TFLOPS["f64"], 4)})
+        if nbytes is not None:
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            r.update({"bytes": nbytes, "GB/s": round(gbs, 1), "frac_hbm": round(gbs / 8000.0, 4)})
+        if note:
+            r["flop_count"] = note
+        out[name] = r
+        log(f"ops {name}: {json.dumps(r)}")
+
+    n = 16384
+    c = W.tri(n)
+    L = torch.from_numpy(c["L"]).to(dev)
+    del c
+    X = torch.empty_like(L)
+    rec(f"trtri-n{n}", med_ms(lambda: O.trtri(H, L, X)), n ** 3 / 3.0, note="n^3/3")
+    n2 = 8192
+    L2 = L[:n2, :n2].contiguous()
+    X2 = O.trtri(H, L2)
+    Xb2 = torch.tril(torch.randn(n2, n2, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(7)))
+    Lb2 = torch.empty_like(L2)
+    rec(f"trtri_adjoint-n{n2}", med_ms(lambda: O.trtri_adjoint(H, X2, Xb2, Lb2)), float(n2) ** 3,
+        note="n^3 (two triangular-by-triangular products)")
+    del X2, Xb2, Lb2, L2
+    r = 64
+    Bm = torch.randn(n, r, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(8))
+    C = Bm.clone()
+    H.trsm(L, C)
+    Cb0 = torch.randn(n, r, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(9))
+    Cb = Cb0.clone()
+    Lb = torch.empty_like(L)
+
+    def tadj():
+        Cb.copy_(Cb0)
+        O.trsm_adjoint(H, L, C, Cb, False, Lb)
+    rec(f"trsm_adjoint-n{n}-r{r}", med_ms(tadj), 2.0 * n * n * r, note="2 n^2 r (solve n^2 r + tril(Bbar C^T) n^2 r)")
+    del L, X, Bm, C, Cb0, Cb, Lb
+    torch.cuda.empty_cache()
+    m = 8192
+    g = torch.Generator(dev).manual_seed(10)
+    A = torch.randn(m, m, dtype=torch.float64, device=dev, generator=g)
+    B = torch.randn(m, m, dtype=torch.float64, device=dev, generator=g)
+    Cm = torch.empty_like(A)
+    rec(f"gemm-{m}x{m}x{m}", med_ms(lambda: O.gemm(H, A, B, C=Cm)), 2.0 * m ** 3, note="2MNK")
+    Ab, Bb = torch.empty_like(A), torch.empty_like(B)
+    rec(f"gemm_adjoint-{m}x{m}x{m}", med_ms(lambda: O.gemm_adjoint(H, A, B, Cm, Abar=Ab, Bbar=Bb)),
+        4.0 * m ** 3, note="4MNK (Abar and Bbar)")
+    del Ab, Bb
+    rec(f"multiply_transpose-{m}x{m}", med_ms(lambda: O.multiply_transpose(H, A, Cm)), float(m) * (m + 1) * m,
+        note="M(M+1)K (lower tiles, mirrored)")
+    del A, B, Cm
+    torch.cuda.empty_cache()
+    Ms, Ks = 256, 262144
+    As = torch.randn(Ms, Ks, dtype=torch.float64, device=dev, generator=g)
+    Bs = torch.randn(Ks, Ms, dtype=torch.float64, device=dev, generator=g)
+    Cs = torch.empty(Ms, Ms, dtype=torch.float64, device=dev)
+    ms_s = med_ms(lambda: O.gemm(H, As, Bs, C=Cs))
+    rec(f"gemm_splitk-{Ms}x{Ms}x{Ks}", ms_s, 2.0 * Ms * Ms * Ks, note=f"2MNK, {O.last_splits(H)} k-slices")
+    del As, Bs, Cs
+    torch.cuda.empty_cache()
+    for (nn, kk) in ((1000000, 100), (100000, 1000)):
+        gl = W.glm(nn, kk)
+        Xg = torch.from_numpy(gl["X"]).to(dev)
+        yg = torch.from_numpy(gl["y"]).to(dev)
+        al = torch.tensor(gl["alpha"], dtype=torch.float64, device=dev)
+        be = torch.from_numpy(gl["beta"]).to(dev)
+        del gl
+        by = 8.0 * nn * kk + 4.0 * nn
+        rec(f"glm_bernoulli_logit-n{nn}-k{kk}", med_ms(lambda: O.glm_bernoulli_logit(H, Xg, yg, al, be)),
+            nbytes=by)
+        rec(f"glm_bernoulli_logit-n{nn}-k{kk}-with-dX",
+            med_ms(lambda: O.glm_bernoulli_logit(H, Xg, yg, al, be, with_dX=True)), nbytes=by + 8.0 * nn * kk)
+        del Xg, yg, al, be
+        torch.cuda.empty_cache()
+    del H
+    return out
+
+
 def timed(fn, steps, warmup, what=""):
     import torch
     for i in range(warmup):
@@ -152,6 +264,30 @@ def timed(fn, steps, warmup, what=""):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def mixed_step(args, A0, Lb0, y0, info, ld):
+    """The mixed-form step on the headline workload: restore the covariance,
+    factor with FP32 trailing updates, FP64-refined solve of K alpha = y,
+    log-det, restore the adjoint seed, adjoint.  Returns (step, L, Abar, x,
+    handle, out) with out holding the last refinement's (x, iters, eta)."""
+    import torch
+    from paper_1907_01063_amd import GPC_MIXED, Handle
+    Lm, Lbm = torch.empty_like(A0), torch.empty_like(Lb0)
+    xr = torch.empty_like(y0)
+    Hm = Handle()
+    Hm.set_options(block=args.block, precision=GPC_MIXED, lookahead=args.lookahead)
+    out = {}
+
+    def stepmix():
+        Lm.copy_(A0)
+        Hm.factor(Lm, info)
+        out["x"], out["it"], out["eta"] = Hm.solve_refined(A0, Lm, y0, x=xr, check=False)
+        Hm.logdet(Lm, ld)
+        Lbm.copy_(Lb0)
+        Hm.adjoint(Lm, Lbm)
+
+    return stepmix, Lm, Lbm, xr, Hm, out
 
 
 def main():
@@ -174,6 +310,9 @@ def main():
     ap.add_argument("--serial-classes", action="store_true",
                     help="also trace one step with lookahead off (per-class kernel times, each kernel alone)")
     ap.add_argument("--headline-only", action="store_true")
+    ap.add_argument("--no-ops", action="store_true", help="skip the operations beside the factor")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="run only the mixed-form step (for profiler runs; prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
@@ -201,6 +340,14 @@ def main():
     H = Handle()
     H.set_options(block=args.block, precision=GPC_FP64, lookahead=args.lookahead)
     F = W.flops_factor(n) + W.flops_adjoint(n)
+
+    if args.mixed_only:
+        # the mixed step alone, for profiler runs of its kernels (no headline)
+        stepmix = mixed_step(args, A0, Lb0, y0, info, ld)[0]
+        msm = timed(stepmix, args.steps, args.warmup, "mixed")
+        print(json.dumps({"form": "mixed", "workload": f"matern32-2d-n{n}", "ms_per_step": round(msm, 3),
+                          "GFLOP/s": round(F / (msm * 1e-3) / 1e9, 2)}), flush=True)
+        return
 
     def step64():
         L.copy_(A0)
@@ -288,20 +435,7 @@ def main():
 
     if not args.headline_only:
         # ---- mixed form with the FP64-refined solve
-        Lm, Lbm = torch.empty_like(A0), torch.empty_like(Lb0)
-        xr = torch.empty_like(y0)
-        Hm = Handle()
-        Hm.set_options(block=args.block, precision=GPC_MIXED, lookahead=args.lookahead)
-        out = {}
-
-        def stepmix():
-            Lm.copy_(A0)
-            Hm.factor(Lm, info)
-            out["x"], out["it"], out["eta"] = Hm.solve_refined(A0, Lm, y0, x=xr, check=False)
-            Hm.logdet(Lm, ld)
-            Lbm.copy_(Lb0)
-            Hm.adjoint(Lm, Lbm)
-
+        stepmix, Lm, Lbm, xr, Hm, out = mixed_step(args, A0, Lb0, y0, info, ld)
         log(f"mixed: {args.warmup} warmup + {args.steps} timed steps")
         msm = timed(stepmix, args.steps, args.warmup, "mixed")
         Hm.check()
@@ -428,6 +562,10 @@ def main():
                      "evals_timed": args.gp_evals, **gp}
         del X, Y, Hg
         torch.cuda.empty_cache()
+
+    if not args.headline_only and not args.no_ops:
+        log("operations beside the factor")
+        cfg["ops"] = ops_bench()
 
     cpu = None
     if not args.no_cpu_baseline:

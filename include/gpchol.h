@@ -77,6 +77,10 @@ typedef struct {
                               its solution entries are NaN, which tests the failure path */
     int32_t gemm_max_splits; /* largest split-K count of gpc_gemm (gpchol_ops.h); 0 = 32
                                 (default), 1 = never split */
+    int32_t batched_schedule; /* batched calls: 0 = library choice (default: grouped when the
+                                 largest member has order >= 256, else persistent);
+                                 1 = persistent (one workgroup per matrix, one launch);
+                                 2 = grouped (every block step one launch over all members) */
 } gpc_options;
 
 typedef struct gpc_handle gpc_handle;
@@ -198,13 +202,19 @@ gpc_status gpc_gp_hypergrad_se(gpc_handle* h, int64_t n, int32_t d, const double
 
 /* Batched forms: nb matrices of uneven order n_host[i] (>= 0), each stored
  * row-major with leading dimension n_host[i] at element offset off_host[i]
- * from the base pointer (the caller keeps them disjoint).  One persistent
- * launch handles the whole batch: workgroups take matrices from a device
- * queue, largest first, and factor / differentiate each alone (the same
- * blocked algorithms as gpc_factor / gpc_adjoint, inner block chosen per size
- * bucket by gpc_autotune_batched, default 64).  The launch is captured once
- * into a HIP graph per distinct (sizes, offsets, pointers) and replayed on
- * later calls.  If the handle's stream is itself being captured, the launch
+ * from the base pointer (the caller keeps them disjoint).  Two schedules
+ * (gpc_options.batched_schedule) run the same blocked algorithms as
+ * gpc_factor / gpc_adjoint (section 3.3) on every member:
+ *  - persistent: one launch; workgroups take matrices from a device queue,
+ *    largest first, and factor / differentiate each alone (inner block chosen
+ *    per size bucket by gpc_autotune_batched, default 64);
+ *  - grouped (the default once a member has order >= 256): block size 64,
+ *    every block step one launch over all members that have it (the
+ *    diagonal blocks one workgroup each, the products one workgroup per
+ *    64 x 64 output tile of every member), so a large member is spread over
+ *    many CUs.
+ * The launches are captured once into a HIP graph per distinct (sizes,
+ * offsets, pointers, schedule) and replayed on later calls.  If the handle's stream is itself being captured, the launch
  * is recorded into the caller's graph instead, provided the same call (same
  * sizes, offsets and pointers) has been made once outside the capture, which
  * prepares its plan; otherwise the call returns GPC_ERR_CAPTURE and enqueues

@@ -35,6 +35,8 @@ struct BatchPlan {
     hipGraphExec_t exec = nullptr;
     double flops = 0.0;
     bool pinned = false;   // recorded into a caller's graph: its buffers must outlive that graph
+    int schedule = 1;      // 1 persistent, 2 grouped
+    gpc::GroupedSchedule* grouped = nullptr;
 };
 
 struct gpc_handle {
@@ -69,6 +71,8 @@ namespace {
 using namespace gpc;
 
 constexpr int kDefaultBlock = 256;
+// Batched calls take the grouped schedule by default once a member is this large.
+constexpr int kGroupedMinN = 256;
 
 gpc_status hip_fail(gpc_handle* h, hipError_t e, const char* what)
 {
@@ -147,6 +151,7 @@ void free_plan(BatchPlan* p)
     if (p->d_tasks) hipFree(p->d_tasks);
     if (p->d_counter) hipFree(p->d_counter);
     if (p->d_ws) hipFree(p->d_ws);
+    gpc::grouped_free(p->grouped);
     delete p;
 }
 
@@ -236,6 +241,11 @@ bool overlap(const void* a, int64_t ra, int64_t ca, int64_t lda, const void* b, 
 // workgroups past a full round takes two rounds, which the plan avoids.
 void splitk_plan(int64_t tiles, int64_t K, int max_splits, int64_t slots, int* splits, int64_t* chunk)
 {
+    if (K <= 0) {   // nothing to split (and no chunk to divide by)
+        *splits = 1;
+        *chunk = 32;
+        return;
+    }
     int64_t best_s = 1, best_c = std::max<int64_t>(32, (K + 31) / 32 * 32);
     double best = -1.0;
     for (int64_t s = 1; s <= max_splits; ++s) {
@@ -267,6 +277,13 @@ TileCfg skinny_tile(int64_t M, int64_t N)
 {
     const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128);
     return t128 < 256 ? TILE_64 : TILE_128;
+}
+
+// In-place panel products (one tile column spanning all of N <= 128): 64-row
+// tiles while 128-row ones would leave CUs without a workgroup.
+TileCfg panel_tile(int64_t M, int cus)
+{
+    return (M + 127) / 128 < 2 * (int64_t)cus ? TILE_64W : TILE_128;
 }
 
 GemmArgs gemm_args(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
@@ -469,6 +486,7 @@ gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
     if (o->mixed_fallback != 0 && o->mixed_fallback != 1) return GPC_ERR_ARG;
     if (o->test_flags != 0 && o->test_flags != 1) return GPC_ERR_ARG;
     if (o->gemm_max_splits < 0 || o->gemm_max_splits > kGemmMaxSplits) return GPC_ERR_ARG;
+    if (o->batched_schedule < 0 || o->batched_schedule > 2) return GPC_ERR_ARG;
     h->opt = *o;
     return GPC_OK;
 }
@@ -551,8 +569,8 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
                     pg.Cf = Pf + (kh + bh - k) * B + h0;
                     pg.ldcf = B;
                 }
-                // in place: one 128-wide tile column, so no tile writes columns another reads
-                GPC_HIP(h, gemm_f64(s, TILE_128, false, true, EPI_STORE, false, pg, 1));
+                // in place: one tile column spans all 128 columns, so no tile writes columns another reads
+                GPC_HIP(h, gemm_f64(s, panel_tile(m, h->cus), false, true, EPI_STORE, false, pg, 1));
             }
             if (h0 + bh < kB) {   // the rest of this outer block
                 const int nh = kB - h0 - bh;
@@ -791,7 +809,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
                     g5.Cf = Cf;
                     g5.ldcf = b;
                 }
-                GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g5, 1));
+                GPC_HIP(h, gemm_f64(s, panel_tile(nr, h->cus), false, false, EPI_STORE, false, g5, 1));
                 if (bq > hb) {
                     GemmArgs g5b = gemm_args(nr, bq - hb, bq - hb, Cbar + hb, ldlb, Dq_inv + hb * b + hb, b,
                                              Cbar + hb, ldlb);
@@ -799,7 +817,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
                         g5b.Cf = Cf + hb;
                         g5b.ldcf = b;
                     }
-                    GPC_HIP(h, gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g5b, 1));
+                    GPC_HIP(h, gemm_f64(s, panel_tile(nr, h->cus), false, false, EPI_STORE, false, g5b, 1));
                 }
             }
             int64_t ch;
@@ -1089,9 +1107,11 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
     GPC_HIP(h, hipStreamIsCapturing(s, &cs));
     const bool capturing = cs != hipStreamCaptureStatusNone;
     std::vector<int32_t> blocks(h->tune_block, h->tune_block + kTuneBuckets);
+    int schedule = h->opt.batched_schedule;
+    if (schedule == 0) schedule = *std::max_element(n_host, n_host + nb) >= kGroupedMinN ? 2 : 1;
     BatchPlan* p = h->plan;
     const bool same = p && p->mode == mode && p->A == A && p->Lb == Lb && p->info == info &&
-                      p->blocks == blocks && p->n.size() == (size_t)nb &&
+                      p->blocks == blocks && p->schedule == schedule && p->n.size() == (size_t)nb &&
                       std::equal(p->n.begin(), p->n.end(), n_host) && std::equal(p->off.begin(), p->off.end(), off_host);
     if (!same) {
         // a new plan waits for the stream and allocates: not possible while
@@ -1111,6 +1131,7 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
         p->n.assign(n_host, n_host + nb);
         p->off.assign(off_host, off_host + nb);
         p->blocks = blocks;
+        p->schedule = schedule;
         std::vector<gpc::BatchTask> tasks(nb);
         for (int32_t i = 0; i < nb; ++i) {
             tasks[i].n = n_host[i];
@@ -1124,15 +1145,22 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
         }
         std::stable_sort(tasks.begin(), tasks.end(),
                          [](const gpc::BatchTask& a, const gpc::BatchTask& b) { return a.n > b.n; });
-        p->wgs = std::min<int>(nb, 2 * h->cus);
-        GPC_HIP(h, hipMalloc(&p->d_tasks, sizeof(gpc::BatchTask) * nb));
-        GPC_HIP(h, hipMalloc(&p->d_counter, sizeof(int32_t)));
-        GPC_HIP(h, hipMalloc(&p->d_ws, sizeof(double) * gpc::batched_scratch_doubles(p->wgs)));
-        GPC_HIP(h, hipMemcpy(p->d_tasks, tasks.data(), sizeof(gpc::BatchTask) * nb, hipMemcpyHostToDevice));
+        if (schedule == 2) {
+            hipError_t ge = hipSuccess;
+            p->grouped = gpc::grouped_prepare(nb, tasks.data(), A, Lb, info, mode, &ge);
+            if (!p->grouped) return hip_fail(h, ge, "grouped batched schedule");
+        } else {
+            p->wgs = std::min<int>(nb, 2 * h->cus);
+            GPC_HIP(h, hipMalloc(&p->d_tasks, sizeof(gpc::BatchTask) * nb));
+            GPC_HIP(h, hipMalloc(&p->d_counter, sizeof(int32_t)));
+            GPC_HIP(h, hipMalloc(&p->d_ws, sizeof(double) * gpc::batched_scratch_doubles(p->wgs)));
+            GPC_HIP(h, hipMemcpy(p->d_tasks, tasks.data(), sizeof(gpc::BatchTask) * nb, hipMemcpyHostToDevice));
+        }
         if (!h->cap_stream) GPC_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         GPC_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t le = gpc::batched_launch(h->cap_stream, nb, p->d_tasks, A, Lb, info, p->d_counter, p->d_ws,
-                                            p->wgs, mode);
+        hipError_t le = schedule == 2 ? gpc::grouped_enqueue(p->grouped, h->cap_stream, info)
+                                      : gpc::batched_launch(h->cap_stream, nb, p->d_tasks, A, Lb, info, p->d_counter,
+                                                            p->d_ws, p->wgs, mode);
         hipGraph_t g = nullptr;
         hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
         p->graph = g;
@@ -1147,7 +1175,8 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
         // the caller is capturing: record the launch into its graph instead;
         // the plan's buffers then stay allocated until gpc_destroy
         p->pinned = true;
-        GPC_HIP(h, gpc::batched_launch(s, nb, p->d_tasks, A, Lb, info, p->d_counter, p->d_ws, p->wgs, mode));
+        if (p->schedule == 2) GPC_HIP(h, gpc::grouped_enqueue(p->grouped, s, info));
+        else GPC_HIP(h, gpc::batched_launch(s, nb, p->d_tasks, A, Lb, info, p->d_counter, p->d_ws, p->wgs, mode));
     }
     return GPC_OK;
 }
@@ -1185,6 +1214,13 @@ gpc_status gpc_autotune_batched(gpc_handle* h, const char* cache_path)
     if (cs != hipStreamCaptureStatusNone) return GPC_ERR_CAPTURE;
     const int mids[kTuneBuckets] = {80, 192, 384, 768, 1024};
     const int cnt = 16;
+    // the inner block belongs to the persistent schedule: time that one
+    struct ScheduleGuard {
+        gpc_handle* h;
+        int32_t saved;
+        ~ScheduleGuard() { h->opt.batched_schedule = saved; }
+    } guard{h, h->opt.batched_schedule};
+    h->opt.batched_schedule = 1;
     for (int bk = 0; bk < kTuneBuckets; ++bk) {
         const int64_t n = mids[bk];
         std::vector<int32_t> ns(cnt, (int32_t)n);

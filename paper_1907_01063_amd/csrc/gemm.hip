@@ -17,6 +17,8 @@
 // The result rows differ by type (measured on gfx950): the FP64 instruction
 // puts element (l/16 + 4r, l%16) in accumulator slot r, the FP32 instruction
 // puts element (4*(l/16) + r, l%16) there.
+#include <stdlib.h>
+
 #include "gemm_tile.hpp"
 
 namespace gpc {
@@ -34,11 +36,16 @@ gemm_kernel(GemmArgs g)
     const int t = w < per * 8 ? (w % 8) * per + w / 8 : w;
     int64_t tm, tn;
     if (LOWER) {
-        lower_tile(t, tm, tn);
+        if (g.group > 1) grouped_lower_tile(t, (g.M + BM - 1) / BM, g.group, tm, tn);
+        else lower_tile(t, tm, tn);
     } else {
         const int tilesN = (int)((g.N + BN - 1) / BN);
-        tm = t / tilesN;
-        tn = t % tilesN;
+        if (g.group > 1) {
+            grouped_tile(t, (g.M + BM - 1) / BM, tilesN, g.group, tm, tn);
+        } else {
+            tm = t / tilesN;
+            tn = t % tilesN;
+        }
     }
     // tile coordinates are uniform: keep them (and all that derives from
     // them) in scalar registers
@@ -50,6 +57,28 @@ gemm_kernel(GemmArgs g)
     gb.B = (const TI*)g.B + blockIdx.y * g.bsB;
     gb.C = g.C + blockIdx.y * g.bsC;
     gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(gb, tm, tn, blockIdx.z, lds);
+}
+
+// Row panels kept per XCD by the grouped tile order: as many BM-row panels
+// of the launch's k-chunk as fit in `group_bytes` (at most 16).  The budget
+// is half of an XCD's 4 MiB L2 by default; the environment variable
+// GPC_TILE_GROUP_KIB sets it (0 = row-by-row order), read once per process.
+int64_t group_bytes()
+{
+    static const int64_t v = [] {
+        const char* e = getenv("GPC_TILE_GROUP_KIB");
+        return e ? (int64_t)atoll(e) * 1024 : (int64_t)2048 * 1024;
+    }();
+    return v;
+}
+
+template <typename TI, int BM>
+int tile_group(const GemmArgs& g)
+{
+    const int64_t kc = g.kchunk < g.K ? g.kchunk : g.K;
+    const int64_t panel = (int64_t)BM * (kc > 0 ? kc : 1) * (int64_t)sizeof(TI);
+    const int64_t G = group_bytes() / panel;
+    return (int)(G < 2 ? 1 : G > 16 ? 16 : G);
 }
 
 template <typename TI, int BM, int BN, int BK, int WM, int WN, bool AKM, bool BNK, int EPI, bool LOWER>
@@ -64,7 +93,9 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits, int batch)
         tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     }
     dim3 grid((unsigned)tiles, (unsigned)(batch < 1 ? 1 : batch), (unsigned)(splits < 1 ? 1 : splits));
-    hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>), grid, dim3(WM * WN * 64), 0, s, g);
+    GemmArgs ga = g;
+    ga.group = tile_group<TI, BM>(g);
+    hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>), grid, dim3(WM * WN * 64), 0, s, ga);
     return hipGetLastError();
 }
 
@@ -80,7 +111,7 @@ bool ld_fits(const GemmArgs& g)
 
 #define GPC_GEMM_CASE(TI, CFG, BM, BN, BK, AKM, BNK, EPI, LOWER)                                 \
     if (cfg == CFG && a_km == AKM && b_nk == BNK && epi == EPI && lower_tiles == LOWER)           \
-        return launch<TI, BM, BN, BK, (BM == 128 ? 2 : 2), (BM == 128 ? 4 : 2), AKM, BNK, EPI, LOWER>(s, g, splits, batch);
+        return launch<TI, BM, BN, BK, 2, (BN == 128 ? 4 : 2), AKM, BNK, EPI, LOWER>(s, g, splits, batch);
 
 hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, bool lower_tiles,
                     const GemmArgs& g, int splits, int batch)
@@ -95,6 +126,9 @@ hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, b
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, false, EPI_SUB, false)
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, false, EPI_PARTIAL, false)
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_PARTIAL, false)
+    // panel solves with twice the workgroups (64-row tiles spanning all N)
+    GPC_GEMM_CASE(double, TILE_64W, 64, 128, 16, false, true, EPI_STORE, false)
+    GPC_GEMM_CASE(double, TILE_64W, 64, 128, 16, false, false, EPI_STORE, false)
     // skinny narrow update (more, smaller tiles)
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, false, true, EPI_SUB, false)
     // diagonal-block reverse step

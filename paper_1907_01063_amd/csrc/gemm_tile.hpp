@@ -5,6 +5,7 @@
 #include <type_traits>
 
 #include "internal.hpp"
+#include "tile_order.hpp"
 
 namespace gpc {
 
@@ -49,16 +50,6 @@ template <> __device__ __forceinline__ float buffer_ld<float>(__amdgpu_buffer_rs
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
 
-// Tile (ti, tj), tj <= ti, of index b in the row-by-row enumeration of the
-// lower triangle of tiles.
-__device__ __forceinline__ void lower_tile(int64_t b, int64_t& ti, int64_t& tj)
-{
-    int64_t t = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-    while (t * (t + 1) / 2 > b) --t;
-    while ((t + 1) * (t + 2) / 2 <= b) ++t;
-    ti = t;
-    tj = b - t * (t + 1) / 2;
-}
 
 template <typename TI, int BM, int BN, int BK>
 struct TileLds {

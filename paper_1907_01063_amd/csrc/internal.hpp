@@ -42,9 +42,12 @@ struct GemmArgs {
     int32_t c_lower;          // nonzero: never write C elements with col > row (C-local indices)
     int64_t bsA, bsB, bsC;    // batch strides (elements) applied per blockIdx.y
     int32_t negate;           // EPI_STORE: store -acc
+    int32_t group;            // tile order: bands of `group` tile rows (0/1 = row by row); set by the launcher
 };
 
-enum TileCfg : int { TILE_128 = 0, TILE_64 = 1 };
+// TILE_64W: 64 x 128 tiles of 8 waves (twice the workgroups of TILE_128 for
+// the in-place panel products, whose one tile column must span all N)
+enum TileCfg : int { TILE_128 = 0, TILE_64 = 1, TILE_64W = 2 };
 
 // Launchers (hipError_t from the launch).  `lower_tiles`: M == N and only tiles
 // on or below the diagonal are computed, and only elements with m >= n written.
@@ -177,5 +180,14 @@ int64_t batched_scratch_doubles(int wgs);
 hipError_t batched_launch(hipStream_t s, int nb, const BatchTask* tasks, double* Abase, double* Lbbase,
                           int32_t* info, int32_t* counter, double* ws, int wgs, int mode);
 hipError_t spd_test_fill(hipStream_t s, int64_t n, double* A, double* Lb, int64_t off);
+
+// Grouped schedule of the batched calls (grouped.hip): every block step one
+// launch over all members.  prepare allocates and uploads the descriptors
+// (synchronous); enqueue records the launches on a stream; free releases.
+struct GroupedSchedule;
+GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, double* Lbbase, int32_t* info,
+                                 int mode, hipError_t* err);
+hipError_t grouped_enqueue(const GroupedSchedule* g, hipStream_t s, int32_t* info);
+void grouped_free(GroupedSchedule* g);
 
 }  // namespace gpc

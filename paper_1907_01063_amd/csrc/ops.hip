@@ -329,6 +329,11 @@ hipError_t trtri_full(hipStream_t s, int64_t n, const double* L, int64_t ldl, do
 // sum a third of a unit per tile and split.
 void plan_split_k(int64_t tiles, int64_t K, int max_splits, int64_t slots, int* splits, int64_t* chunk)
 {
+    if (K <= 0) {   // nothing to split (and no chunk to divide by)
+        *splits = 1;
+        *chunk = 32;
+        return;
+    }
     int64_t best_s = 1, best_c = std::max<int64_t>(32, (K + 31) / 32 * 32);
     double best = -1.0;
     for (int64_t sp = 1; sp <= max_splits; ++sp) {

@@ -49,7 +49,8 @@ class gpc_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("lookahead", ctypes.c_int32), ("refine_maxit", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("mixed_fallback", ctypes.c_int32),
-                ("test_flags", ctypes.c_int32), ("gemm_max_splits", ctypes.c_int32)]
+                ("test_flags", ctypes.c_int32), ("gemm_max_splits", ctypes.c_int32),
+                ("batched_schedule", ctypes.c_int32)]
 
 
 _i64, _i32, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
@@ -110,7 +111,9 @@ def _ptr(t) -> int:
 def _mat(t: torch.Tensor, name: str):
     if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.dim() != 2 or not t.is_cuda:
         raise TypeError(f"{name}: expected a 2-D float64 GPU tensor")
-    if t.shape[0] != 0 and t.shape[1] > 1 and t.stride(1) != 1:
+    if t.numel() == 0:   # no element is addressed: the smallest valid row stride
+        return max(1, t.shape[1])
+    if t.shape[1] > 1 and t.stride(1) != 1:
         raise ValueError(f"{name}: needs unit column stride (row-major)")
     return t.stride(0) if t.shape[0] > 1 else max(1, t.shape[1])
 

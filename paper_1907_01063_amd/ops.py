@@ -151,6 +151,8 @@ def glm_bernoulli_logit(H: Handle, X, y, alpha, beta, with_dX=False):
     n, k = X.shape
     if y.dtype != torch.int32:
         raise TypeError("y must be int32")
+    if alpha.dtype != torch.float64 or beta.dtype != torch.float64:
+        raise TypeError("alpha and beta must be float64")
     alpha = alpha.reshape(()).contiguous()
     beta = beta.contiguous()
     lp = torch.empty((), dtype=torch.float64, device=X.device)
@@ -179,7 +181,7 @@ class TriangularSolve(torch.autograd.Function):
     def backward(ctx, Cbar):
         L, C = ctx.saved_tensors
         Bbar = Cbar.detach().clone().contiguous()
-        Lbar = ctx.trsm_adjoint(ctx.H, L, C, Bbar, trans=ctx.trans)
+        Lbar = trsm_adjoint(ctx.H, L, C, Bbar, trans=ctx.trans)
         return Lbar, Bbar, None, None
 
 

@@ -1,6 +1,7 @@
-"""Batched persistent path: many uneven matrices in one launch (graph replay),
-against the oracle per matrix, with results that must not depend on queue
-order or on replay."""
+"""Batched path, both schedules (persistent: one workgroup per matrix in one
+launch; grouped: every block step one launch over all members), graph
+replayed: against the oracle per matrix, with results that must not depend
+on queue order or on replay."""
 import numpy as np
 import pytest
 import torch
@@ -14,10 +15,12 @@ pytestmark = pytest.mark.gpu
 SIZES = [1, 5, 31, 32, 33, 63, 64, 65, 100, 128, 129, 200, 257, 300, 0, 17]
 
 
-@pytest.fixture(scope="module")
-def H():
+@pytest.fixture(scope="module", params=[1, 2], ids=["persistent", "grouped"])
+def H(request):
     from paper_1907_01063_amd import Handle
-    return Handle()
+    h = Handle()
+    h.set_options(batched_schedule=request.param)
+    return h
 
 
 def pack(mats, align=32):
@@ -142,7 +145,8 @@ def test_full_size_batch_sampled(H):
         assert relf(lb[o:o + k * k].reshape(k, k), oracle.potrf_adjoint(Lo, Lb)) <= TOL
 
 
-def test_batched_mixed_form():
+@pytest.mark.parametrize("schedule", [1, 2], ids=["persistent", "grouped"])
+def test_batched_mixed_form(schedule):
     """GPC_MIXED batch: FP32 trailing / B-bar / R-bar products.  No oracle of
     its own (parity unpinned): error against the FP64 oracle within the mixed
     budget of the single-matrix tests (L 1e-3, Abar 1e-2), nonzero (the FP32
@@ -150,7 +154,7 @@ def test_batched_mixed_form():
     independent, and bitwise stable across graph replays."""
     from paper_1907_01063_amd import GPC_MIXED, Handle
     Hm = Handle()
-    Hm.set_options(precision=GPC_MIXED)
+    Hm.set_options(precision=GPC_MIXED, batched_schedule=schedule)
     As, Lbs = make_batch(6, SIZES)
     say("batched mixed")
     Ls, Abs, info = run(Hm, As, Lbs, SIZES)
@@ -174,7 +178,8 @@ def test_batched_mixed_form():
         assert np.array_equal(Ls3[pos], Ls[i]) and np.array_equal(Ab3[pos], Abs[i])
 
 
-def test_batched_recorded_into_caller_graph():
+@pytest.mark.parametrize("schedule", [1, 2], ids=["persistent", "grouped"])
+def test_batched_recorded_into_caller_graph(schedule):
     """A batched call inside the caller's graph capture: refused (nothing
     enqueued, the capture stays usable) when its plan was not prepared by the
     same call outside the capture; recorded when it was.  The caller's graph
@@ -183,6 +188,7 @@ def test_batched_recorded_into_caller_graph():
     from paper_1907_01063_amd import GpcError, Handle
     from paper_1907_01063_amd.gpchol import GPC_ERR_CAPTURE
     Hc = Handle()
+    Hc.set_options(batched_schedule=schedule)
     sizes = SIZES[:8]
     As, Lbs = make_batch(7, sizes)
     a, off = pack(As)

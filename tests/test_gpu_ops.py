@@ -143,11 +143,15 @@ def test_multiply_transpose_parity(H, M, K):
 
 # ---- GLM ------------------------------------------------------------------------------
 
+def alpha_of(c):
+    return torch.tensor(c["alpha"], dtype=torch.float64, device="cuda")
+
+
 @pytest.mark.parametrize("n,k", [(0, 5), (1, 1), (37, 3), (1000, 10), (5000, 100), (3000, 2048), (2000, 3000)])
 def test_glm_parity(H, n, k):
     c = W.glm(n, k)
-    lp, da, db, dX = ops().glm_bernoulli_logit(H, dev(c["X"]), dev(c["y"]), torch.tensor(c["alpha"]).cuda(),
-                                               dev(c["beta"]), with_dX=True)
+    lp, da, db, dX = ops().glm_bernoulli_logit(H, dev(c["X"]), dev(c["y"]), alpha_of(c), dev(c["beta"]),
+                                               with_dX=True)
     lpo, dao, dbo, dXo = oracle.glm_bernoulli_logit(c["X"], c["y"], c["alpha"], c["beta"], with_dX=True)
     got = float(host(lp))
     e_lp = abs(got - lpo) / max(abs(lpo), 1.0)
@@ -157,15 +161,14 @@ def test_glm_parity(H, n, k):
     say(f"glm n={n} k={k}: lp {e_lp:.2e} dalpha {e_da:.2e} dbeta {e_db:.2e} dX {e_dx:.2e}")
     assert max(e_lp, e_da, e_db, e_dx) <= TOL
     # bit-for-bit repetition (fixed reduction orders)
-    lp2, _, db2, _ = ops().glm_bernoulli_logit(H, dev(c["X"]), dev(c["y"]), torch.tensor(c["alpha"]).cuda(),
-                                               dev(c["beta"]))
+    lp2, _, db2, _ = ops().glm_bernoulli_logit(H, dev(c["X"]), dev(c["y"]), alpha_of(c), dev(c["beta"]))
     assert float(host(lp2)) == got and np.array_equal(host(db2), host(db))
 
 
 def test_glm_full_size(H):
     c = W.glm(1 << 22, 10)
     Xt = dev(c["X"])
-    lp, da, db, _ = ops().glm_bernoulli_logit(H, Xt, dev(c["y"]), torch.tensor(c["alpha"]).cuda(), dev(c["beta"]))
+    lp, da, db, _ = ops().glm_bernoulli_logit(H, Xt, dev(c["y"]), alpha_of(c), dev(c["beta"]))
     lpo, dao, dbo, _ = oracle.glm_bernoulli_logit(c["X"], c["y"], c["alpha"], c["beta"])
     e = abs(float(host(lp)) - lpo) / abs(lpo)
     say(f"glm n=2^22 k=10: lp {e:.2e} dbeta {relf(host(db), dbo):.2e}")
@@ -192,7 +195,7 @@ def test_autograd_gradcheck(H):
     c = W.glm(50, 4)
     X = torch.tensor(c["X"], device="cuda", requires_grad=True)
     y = torch.tensor(c["y"], device="cuda")
-    al = torch.tensor([c["alpha"]], device="cuda", requires_grad=True)
+    al = torch.tensor([c["alpha"]], dtype=torch.float64, device="cuda", requires_grad=True)
     be = torch.tensor(c["beta"], device="cuda", requires_grad=True)
     assert torch.autograd.gradcheck(lambda x, a, b: BernoulliLogitGLM.apply(x, y, a, b, H), (X, al, be))
 
