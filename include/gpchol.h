@@ -127,6 +127,21 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* opt);
  * the stream is capturing a graph. */
 gpc_status gpc_factor(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info_dev);
 
+/* gpc_factor without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same FP64 factor as gpc_factor with lookahead off:
+ * one stream (the handle's), no ordering events, no launch trace, no growth
+ * of the handle's workspace.  Its only device memory beyond A and info_dev is
+ * a library-owned static array of 128 x 128 doubles (128 KiB per GPU, held
+ * until the process ends) for the inverse of the current diagonal block;
+ * that need does not depend on n, so every n the argument checks accept fits.
+ * All calls on one GPU share that array: calls that overlap in time on the
+ * same GPU (from different streams or handles) race and give wrong results.
+ * Errors: GPC_ERR_ARG as gpc_factor, and when the handle's precision is not
+ * GPC_FP64 (the mixed form needs n-sized FP32 panel copies); GPC_ERR_HIP if
+ * the array's device address cannot be found. */
+gpc_status gpc_factor_noalloc(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info_dev);
+
 /* *fell_back = 1 if the last gpc_factor on this handle was a GPC_MIXED call
  * whose FP32-updated factor failed and was redone in FP64, else 0. */
 gpc_status gpc_get_fallback(const gpc_handle* h, int32_t* fell_back);

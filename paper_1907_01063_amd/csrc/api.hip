@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "gpchol.h"
@@ -65,6 +66,43 @@ struct gpc_handle {
     std::vector<hipEvent_t> ev_pool;   // events owned by the handle
     size_t ev_used = 0;
 };
+
+// ------------------------------------------------------ no-allocation scratch ---
+// Device memory of gpc_factor_noalloc: the inverse of one diagonal block of
+// at most kDiagMax x kDiagMax (128 KiB).  Every GPU the library runs on holds
+// its own copy until the process ends.  Host code never passes the array's
+// name to a kernel: it uses the device address that hipGetSymbolAddress
+// returned for the current device (kept in scratch_dev).
+static __device__ __align__(256) double scratch[gpc::kDiagMax * gpc::kDiagMax];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double* scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev`, looked up once per device with that
+// device current (nullptr on failure; the HIP error is kept in the handle).
+double* scratch_ptr(gpc_handle* h, int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_dev[dev]) return scratch_dev[dev];
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != dev) hipSetDevice(cur);
+    if (e != hipSuccess || !p) {
+        if (h) snprintf(h->err, sizeof(h->err), "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    scratch_dev[dev] = (double*)p;
+    return scratch_dev[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -384,6 +422,12 @@ gpc_status gpc_create(gpc_handle** out, void* stream)
         return GPC_ERR_HIP;
     }
     load_tune_cache(h, getenv("GPC_TUNE_CACHE"));
+    if (!scratch_ptr(h, dev)) {   // the no-allocation entry point's memory on this device
+        hipFree(h->status_dev);
+        hipEventDestroy(h->rebind_ev);
+        delete h;
+        return GPC_ERR_HIP;
+    }
     *out = h;
     return GPC_OK;
 }
@@ -516,7 +560,11 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* o)
 // is zeroed.
 namespace {
 
-gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info, bool mixed)
+// linv_ext: caller-provided room for the diagonal block's inverse (at least
+// kDiagMax^2 doubles); the call then allocates nothing: FP64 only, one
+// stream, no ordering events, no launch trace.
+gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info, bool mixed,
+                       double* linv_ext = nullptr)
 {
     hipStream_t s = h->stream;
     GPC_HIP(h, fill_i32(s, info, 0));
@@ -525,12 +573,16 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
     const int ib = std::min(B, kDiagMax);
     const size_t n_linv = (size_t)ib * ib;
     const size_t n_pf = mixed ? 2 * (size_t)n * B : 0;
-    gpc_status st = ensure_ws(h, sizeof(double) * n_linv + sizeof(float) * n_pf);
-    if (st != GPC_OK) return st;
-    double* Linv = (double*)h->ws;
+    gpc_status st = GPC_OK;
+    double* Linv = linv_ext;
+    if (!Linv) {
+        st = ensure_ws(h, sizeof(double) * n_linv + sizeof(float) * n_pf);
+        if (st != GPC_OK) return st;
+        Linv = (double*)h->ws;
+    }
     float* Pf2 = (float*)(Linv + n_linv);
     const int64_t steps = (n + B - 1) / B;
-    const bool la = h->opt.lookahead != 0 && steps > 2;
+    const bool la = !linv_ext && h->opt.lookahead != 0 && steps > 2;
     hipStream_t s2 = s;
     if (la) {
         if (!h->side) GPC_HIP(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
@@ -692,6 +744,23 @@ gpc_status gpc_get_fallback(const gpc_handle* h, int32_t* fell_back)
     if (!h || !fell_back) return GPC_ERR_ARG;
     *fell_back = h->fell_back;
     return GPC_OK;
+}
+
+gpc_status gpc_factor_noalloc(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t* info)
+{
+    if (!h || n < 0 || !ld_ok(n, lda) || !info || (n > 0 && !A)) return GPC_ERR_ARG;
+    if (h->opt.precision != GPC_FP64) {
+        snprintf(h->err, sizeof(h->err), "gpc_factor_noalloc: FP64 only (the mixed form needs n-sized panels)");
+        return GPC_ERR_ARG;
+    }
+    double* linv = scratch_ptr(h, h->device);
+    if (!linv) return GPC_ERR_HIP;
+    h->fell_back = 0;
+    const bool tr = h->trace;
+    h->trace = false;   // launch tracing takes events from a pool that may grow
+    const gpc_status st = factor_impl(h, n, A, lda, info, false, linv);
+    h->trace = tr;
+    return st;
 }
 
 // --------------------------------------------------------------- adjoint ---

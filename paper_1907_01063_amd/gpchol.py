@@ -25,7 +25,7 @@ GPC_NOTRANS, GPC_TRANS = 0, 1
 # Every symbol the header declares, in declaration order.
 EXPORTS = (
     "gpc_create", "gpc_destroy", "gpc_set_stream", "gpc_check", "gpc_set_options", "gpc_get_options",
-    "gpc_factor", "gpc_get_fallback", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
+    "gpc_factor", "gpc_factor_noalloc", "gpc_get_fallback", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
     "gpc_solve_refined", "gpc_gp_kgen_se", "gpc_gp_value", "gpc_gp_lbar", "gpc_gp_hypergrad_se",
     "gpc_factor_batched", "gpc_adjoint_batched", "gpc_factor_adjoint_batched", "gpc_autotune_batched",
     "gpc_get_tuning",
@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH):
         "gpc_set_options": [_vp, ctypes.POINTER(gpc_options)],
         "gpc_get_options": [_vp, ctypes.POINTER(gpc_options)],
         "gpc_factor": [_vp, _i64, _vp, _i64, _vp],
+        "gpc_factor_noalloc": [_vp, _i64, _vp, _i64, _vp],
         "gpc_adjoint": [_vp, _i64, _vp, _i64, _vp, _i64],
         "gpc_trsm": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _i64],
         "gpc_logdet": [_vp, _i64, _vp, _i64, _vp],
@@ -177,6 +178,17 @@ class Handle:
             info = torch.empty((), dtype=torch.int32, device=A.device)
         self._sync_stream()
         self._check(self.lib.gpc_factor(self.h, n, _ptr(A), lda, _ptr(info)), "gpc_factor")
+        return info
+
+    def factor_noalloc(self, A: torch.Tensor, info: torch.Tensor) -> torch.Tensor:
+        """gpc_factor_noalloc: the FP64 factor in place with no device
+        allocation (the caller passes info as well)."""
+        lda = _mat(A, "A")
+        n = A.shape[0]
+        if A.shape[1] != n:
+            raise ValueError("A must be square")
+        self._sync_stream()
+        self._check(self.lib.gpc_factor_noalloc(self.h, n, _ptr(A), lda, _ptr(info)), "gpc_factor_noalloc")
         return info
 
     def fell_back(self) -> bool:
