@@ -462,6 +462,8 @@ def main():
         cfg["mixed"] = {"value": round(vm, 2), "unit": "GFLOP/s", "ms_per_step": round(msm, 3),
                         "factor_block": args.block or 256,
                         "speedup_vs_fp64": round(ms / msm, 3), "refine_iters": it, "refined_eta_inf": etam,
+                        "frac_of_fp64_peak": round(vm / 1e3 / PEAK_TFLOPS["f64"], 4),
+                        "frac_of_fp32_peak": round(vm / 1e3 / PEAK_TFLOPS["f32"], 4),
                         "phases_ms": phm, "classes_ms_per_step": trm,
                         "err_vs_fp64_path": {"L": eL, "Abar": eA, "alpha": ea},
                         "step": "factor (FP32 trailing updates) + FP64-refined solve + log-det + adjoint"}

@@ -203,6 +203,18 @@ gpc_status gpc_gp_kgen_se(gpc_handle* h, int64_t n, int32_t d, const double* X, 
 gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, const double* y, double* z,
                         double* alpha, double* logdet_dev, double* f_dev);
 
+/* The same pieces when L carries FP32 rounding (GPC_MIXED): alpha solves
+ * K alpha = y by FP64 iterative refinement against K (gpc_solve_refined; its
+ * iters_dev and eta_dev), z = L^T alpha (so that alpha = L^-T z holds for
+ * this L, which keeps gpc_gp_lbar's seed the adjoint of y^T K^-1 y / 2 at
+ * the refined alpha), logdet = 2 sum log L_ii and
+ * f = -1/2 y^T alpha - 1/2 logdet.  K and L: lower triangles read.  Returns
+ * gpc_solve_refined's status (GPC_ERR_REFINE: the outputs are still
+ * written).  z must not overlap alpha, K, L or y. */
+gpc_status gpc_gp_value_refined(gpc_handle* h, int64_t n, const double* K, int64_t ldk, const double* L,
+                                int64_t ldl, const double* y, double* z, double* alpha, double* logdet_dev,
+                                double* f_dev, int32_t* iters_dev, double* eta_dev);
+
 /* Adjoint of the factor for that density: Lbar = tril(alpha z^T) - diag(1/L_ii)
  * (lower triangle; strict upper := 0). */
 gpc_status gpc_gp_lbar(gpc_handle* h, int64_t n, const double* L, int64_t ldl, const double* alpha,

@@ -1067,6 +1067,45 @@ gpc_status gpc_gp_value(gpc_handle* h, int64_t n, const double* L, int64_t ldl, 
     return GPC_OK;
 }
 
+gpc_status gpc_gp_value_refined(gpc_handle* h, int64_t n, const double* K, int64_t ldk, const double* L,
+                                int64_t ldl, const double* y, double* z, double* alpha, double* logdet_out,
+                                double* f_out, int32_t* iters, double* eta)
+{
+    if (!h || n < 0 || !ld_ok(n, ldk) || !ld_ok(n, ldl) || !logdet_out || !f_out || !iters || !eta ||
+        (n > 0 && (!K || !L || !y || !z || !alpha)))
+        return GPC_ERR_ARG;
+    if (overlap(z, 1, n, n, alpha, 1, n, n) || overlap(z, 1, n, n, L, n, n, ldl) ||
+        overlap(z, 1, n, n, K, n, n, ldk) || overlap(z, 1, n, n, y, 1, n, n))
+        return GPC_ERR_ARG;
+    gpc_status st = gpc_solve_refined(h, n, K, ldk, L, ldl, y, alpha, iters, eta);
+    if (st != GPC_OK && st != GPC_ERR_REFINE) return st;
+    hipStream_t s = h->stream;
+    if (n > 0) {
+        // z = L^T alpha from the lower triangle of L: one column of output
+        // tiles with the inner dimension split (fixed-order sum)
+        int sp = 1;
+        int64_t ch = n;
+        splitk_plan((n + 127) / 128, n, 32, 2 * (int64_t)h->cus, &sp, &ch);
+        if (sp > 1) {
+            gpc_status wst = ensure_ws(h, sizeof(double) * (size_t)sp * (size_t)n);
+            if (wst != GPC_OK) return wst;
+        }
+        GemmArgs g = gemm_args(n, 1, n, L, ldl, alpha, 1, sp > 1 ? (double*)h->ws : z, 1);
+        g.a_lower = 1;   // read k-major (L^T); the strict upper part of L is never read
+        if (sp > 1) {
+            g.kchunk = ch;
+            g.pstride = n;
+            GPC_HIP(h, gemm_f64(s, TILE_128, true, false, EPI_PARTIAL, false, g, sp));
+            GPC_HIP(h, reduce_store(s, n, 1, (double*)h->ws, sp, n, 0.0, z, 1));
+        } else {
+            GPC_HIP(h, gemm_f64(s, TILE_128, true, false, EPI_STORE, false, g, 1));
+        }
+    }
+    GPC_HIP(h, logdet(s, n, L, ldl, logdet_out));
+    GPC_HIP(h, gp_value_dot(s, n, y, alpha, logdet_out, f_out));
+    return st;
+}
+
 gpc_status gpc_gp_lbar(gpc_handle* h, int64_t n, const double* L, int64_t ldl, const double* alpha,
                        const double* z, double* Lbar, int64_t ldlb)
 {

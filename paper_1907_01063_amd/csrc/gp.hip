@@ -161,12 +161,12 @@ reduce_parts(int64_t ntiles, int m, const double* part, const double* scale, dou
 }
 
 __global__ void __launch_bounds__(256)
-gp_value_kernel(int64_t n, const double* z, const double* logdet, double* f)
+gp_value_kernel(int64_t n, const double* a, const double* b, const double* logdet, double* f)
 {
     __shared__ double red[256];
     double s = 0.0;
 #pragma unroll 8   // eight loads in flight; the additions keep their order
-    for (int64_t i = threadIdx.x; i < n; i += 256) s += z[i] * z[i];
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += a[i] * b[i];
     s = block_sum(s, red);
     if (threadIdx.x == 0) *f = -0.5 * s - 0.5 * (*logdet);
 }
@@ -355,7 +355,13 @@ hipError_t gp_hypergrad_se(hipStream_t s, int64_t n, int d, const double* X, con
 
 hipError_t gp_value(hipStream_t s, int64_t n, const double* z, const double* logdet, double* f)
 {
-    hipLaunchKernelGGL(gp_value_kernel, dim3(1), dim3(256), 0, s, n, z, logdet, f);
+    hipLaunchKernelGGL(gp_value_kernel, dim3(1), dim3(256), 0, s, n, z, z, logdet, f);
+    return hipGetLastError();
+}
+
+hipError_t gp_value_dot(hipStream_t s, int64_t n, const double* a, const double* b, const double* logdet, double* f)
+{
+    hipLaunchKernelGGL(gp_value_kernel, dim3(1), dim3(256), 0, s, n, a, b, logdet, f);
     return hipGetLastError();
 }
 

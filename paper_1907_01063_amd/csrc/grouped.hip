@@ -60,6 +60,69 @@ __global__ void __launch_bounds__(256) grouped_gemm_kernel(const GemmArgs* args,
     gemm_tile<TI, 64, 64, 16, 2, 2, AKM, BNK, EPI, LOWER, double>(g, tt.tm, tt.tn, 0, lds);
 }
 
+// Two products of one block step in one launch: workgroups [0, n1) take the
+// tiles of list 1 (P = Cbar^T C, long inner dimension, so first), the rest
+// those of list 2 (Bbar -= Cbar R, FP64 or FP32 products).
+template <typename TU>
+__global__ void __launch_bounds__(256) grouped_p_bbar_kernel(const GemmArgs* a1, const GTile* t1, int n1,
+                                                             const GemmArgs* a2, const GTile* t2)
+{
+#if defined(__HIP_DEVICE_COMPILE__)   // the host pass needs only the launch stub
+    __shared__ double lds[TileLds<double, 64, 64, 16>::elems];
+    const int nwg = gridDim.x, w = blockIdx.x, per = nwg / 8;
+    const int t = w < per * 8 ? (w % 8) * per + w / 8 : w;
+    if (t < n1) {
+        const GTile tt = t1[t];
+        const GemmArgs g = a1[tt.arg];
+        gemm_tile<double, 64, 64, 16, 2, 2, true, false, EPI_STORE, false, double>(g, tt.tm, tt.tn, 0, lds);
+    } else {
+        const GTile tt = t2[t - n1];
+        const GemmArgs g = a2[tt.arg];
+        gemm_tile<TU, 64, 64, 16, 2, 2, false, false, EPI_SUB, false, double>(g, tt.tm, tt.tn, 0, (TU*)lds);
+    }
+#endif
+}
+
+// The diagonal step of one member per workgroup: W = tril(Dbar - P),
+// S = sym(D^T W), T = S X, M = X^T T with Dbar <- Phi(M); each product one
+// 64 x 64 tile of the whole workgroup, results visible to it after a barrier.
+struct GDStep {
+    GDiag w;
+    GemmArgs s, t, m;
+};
+
+__global__ void __launch_bounds__(256) grouped_dstep_kernel(const GDStep* d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)   // the host pass needs only the launch stub
+    __shared__ double lds[TileLds<double, 64, 64, 16>::elems];
+    const GDStep* t = d + blockIdx.x;
+    {
+        const GDiag w = t->w;
+        for (int e = threadIdx.x; e < kGB * kGB; e += 256) {
+            const int r = e / kGB, c = e % kGB;
+            double v = 0.0;
+            if (r < w.kb && c <= r) v = w.A[r * w.lda + c] - (w.P ? w.P[r * kGB + c] : 0.0);
+            w.X[e] = v;
+        }
+    }
+    __syncthreads();
+    {
+        const GemmArgs g = t->s;
+        gemm_tile<double, 64, 64, 16, 2, 2, true, false, EPI_SYMLOW, false, double>(g, 0, 0, 0, lds);
+    }
+    __syncthreads();
+    {
+        const GemmArgs g = t->t;
+        gemm_tile<double, 64, 64, 16, 2, 2, false, false, EPI_STORE, false, double>(g, 0, 0, 0, lds);
+    }
+    __syncthreads();
+    {
+        const GemmArgs g = t->m;
+        gemm_tile<double, 64, 64, 16, 2, 2, true, false, EPI_PHI, false, double>(g, 0, 0, 0, lds);
+    }
+#endif
+}
+
 __global__ void __launch_bounds__(256, 2) grouped_potrf_kernel(const GDiag* d)
 {
     __shared__ double F[(kGB / 16) * 256], LU[256];
@@ -112,7 +175,9 @@ enum GOpKind : int {
     G_P,            // <double, KM, KN, STORE>            P = Cbar^T C
     G_S,            // <double, KM, KN, SYMLOW>           S = sym(D^T W)
     G_M,            // <double, KM, KN, PHI>              M = X^T T, Dbar <- Phi(M)
-    G_RBAR          // <TU, KM, KN, SUB>                  Rbar -= [M; Cbar]^T [R; B]
+    G_RBAR,         // <TU, KM, KN, SUB>                  Rbar -= [M; Cbar]^T [R; B]
+    G_P_BBAR,       // P = Cbar^T C and Bbar -= Cbar R in one launch
+    G_DSTEP         // W, S, T, M of the diagonal step, one workgroup per member
 };
 
 }  // namespace
@@ -124,12 +189,14 @@ struct GroupedOp {
     int64_t off;
     int64_t count;
     int64_t off2;   // G_* products: the tile list (the argument array is at off)
+    int64_t off3 = 0, off4 = 0, count1 = 0;   // G_P_BBAR: second list's arguments and tiles; first list's count
 };
 
 struct GroupedSchedule {
     std::vector<GroupedOp> ops;
     void* dbuf = nullptr;
     double* scratch = nullptr;
+    double* invs = nullptr;   // inverses of every 64-block of every member (reverse sweep)
     bool mixed = false;
 };
 
@@ -157,6 +224,16 @@ struct Builder {
         const int64_t oa = put(a);
         ops.push_back({kind, oa, (int64_t)t.size(), put(t)});
     }
+    void gemm2(int kind, const std::vector<GemmArgs>& a1, const std::vector<GTile>& t1,
+               const std::vector<GemmArgs>& a2, const std::vector<GTile>& t2)
+    {
+        if (t1.empty() && t2.empty()) return;
+        GroupedOp op{kind, put(a1), (int64_t)(t1.size() + t2.size()), put(t1)};
+        op.off3 = put(a2);
+        op.off4 = put(t2);
+        op.count1 = (int64_t)t1.size();
+        ops.push_back(op);
+    }
 };
 
 GemmArgs garg(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
@@ -183,6 +260,22 @@ hipError_t launch_gemm(hipStream_t s, const unsigned char* base, const GroupedOp
 {
     hipLaunchKernelGGL((grouped_gemm_kernel<TI, AKM, BNK, EPI, LOWER>), dim3((unsigned)op.count), dim3(256), 0, s,
                        (const GemmArgs*)(base + op.off), (const GTile*)(base + op.off2));
+    return hipGetLastError();
+}
+
+template <typename TU>
+hipError_t launch_p_bbar(hipStream_t s, const unsigned char* base, const GroupedOp& op)
+{
+    hipLaunchKernelGGL(grouped_p_bbar_kernel<TU>, dim3((unsigned)op.count), dim3(256), 0, s,
+                       (const GemmArgs*)(base + op.off), (const GTile*)(base + op.off2), (int)op.count1,
+                       (const GemmArgs*)(base + op.off3), (const GTile*)(base + op.off4));
+    return hipGetLastError();
+}
+
+hipError_t launch_dstep(hipStream_t s, const unsigned char* base, const GroupedOp& op)
+{
+    hipLaunchKernelGGL(grouped_dstep_kernel, dim3((unsigned)op.count), dim3(256), 0, s,
+                       (const GDStep*)(base + op.off));
     return hipGetLastError();
 }
 
@@ -244,10 +337,34 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
         if (!z.empty()) B.ops.push_back({G_ZERO, B.put(z), (int64_t)z.size(), 0});
     }
     if (mode & 2) {
+        // inverses of all diagonal blocks of all members, one launch up front
+        std::vector<int64_t> inv0(nb);
+        int64_t nblk_all = 0;
+        for (int i = 0; i < nb; ++i) {
+            inv0[i] = nblk_all;
+            nblk_all += (tasks[i].n + kGB - 1) / kGB;
+        }
+        e = hipMalloc((void**)&g.invs, sizeof(double) * (size_t)std::max<int64_t>(1, nblk_all * kGB * kGB));
+        if (e != hipSuccess) {
+            *err = e;
+            grouped_free(gp);
+            return nullptr;
+        }
+        auto invp = [&](int i, int q) { return g.invs + (inv0[i] + q) * kGB * kGB; };
+        std::vector<GDiag> inv;
+        for (int i = 0; i < nb; ++i) {
+            const int n = tasks[i].n;
+            const double* L = Abase + tasks[i].off;
+            for (int q = 0; q * kGB < n; ++q) {
+                const int j = q * kGB, bq = std::min(kGB, n - j);
+                inv.push_back({const_cast<double*>(L + (int64_t)j * n + j), nullptr, invp(i, q), nullptr, n, 0, bq, 0});
+            }
+        }
+        B.diag(G_INV, inv);
         for (int s = 0; s < steps; ++s) {
-            std::vector<GDiag> inv, wf;
-            std::vector<GemmArgs> pa, ba, pp, sa, tx, ma, ra;
-            std::vector<GTile> pt, bt, ppt, st, txt, mt, rt;
+            std::vector<GDStep> ds;
+            std::vector<GemmArgs> pa, ba, pp, ra;
+            std::vector<GTile> pt, bt, ppt, rt;
             for (int i = 0; i < nb; ++i) {
                 const int n = tasks[i].n;
                 const int nblk = (n + kGB - 1) / kGB, q = nblk - 1 - s;
@@ -258,9 +375,8 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
                 const double* D = L + (int64_t)j * n + j;
                 double* Dbar = Lb + (int64_t)j * n + j;
                 double* Cbar = Lb + (int64_t)k * n + j;
-                double *X = scr(i, 0), *P = scr(i, 1), *W = scr(i, 2), *S = scr(i, 3), *T = scr(i, 4),
+                double *X = invp(i, q), *P = scr(i, 1), *W = scr(i, 2), *S = scr(i, 3), *T = scr(i, 4),
                        *M = scr(i, 5);
-                inv.push_back({const_cast<double*>(D), nullptr, X, nullptr, n, 0, bq, 0});
                 if (nr > 0) {
                     pa.push_back(garg(nr, bq, bq, Cbar, n, X, kGB, Cbar, n));
                     add_tiles(pt, (int)pa.size() - 1, nr, bq, false);
@@ -271,18 +387,15 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
                     pp.push_back(garg(bq, bq, nr, Cbar, n, L + (int64_t)k * n + j, n, P, kGB));
                     add_tiles(ppt, (int)pp.size() - 1, bq, bq, false);
                 }
-                wf.push_back({Dbar, nr > 0 ? P : nullptr, W, nullptr, n, 0, bq, 0});
-                GemmArgs gs = garg(bq, bq, bq, D, n, W, kGB, S, kGB);
-                gs.a_lower = 1;
-                sa.push_back(gs);
-                add_tiles(st, (int)sa.size() - 1, bq, bq, false);
-                tx.push_back(garg(bq, bq, bq, S, kGB, X, kGB, T, kGB));
-                add_tiles(txt, (int)tx.size() - 1, bq, bq, false);
-                GemmArgs gm = garg(bq, bq, bq, X, kGB, T, kGB, M, kGB);
-                gm.C2 = Dbar;
-                gm.ldc2 = n;
-                ma.push_back(gm);
-                add_tiles(mt, (int)ma.size() - 1, bq, bq, false);
+                GDStep d{};
+                d.w = {Dbar, nr > 0 ? P : nullptr, W, nullptr, n, 0, bq, 0};
+                d.s = garg(bq, bq, bq, D, n, W, kGB, S, kGB);
+                d.s.a_lower = 1;
+                d.t = garg(bq, bq, bq, S, kGB, X, kGB, T, kGB);
+                d.m = garg(bq, bq, bq, X, kGB, T, kGB, M, kGB);
+                d.m.C2 = Dbar;
+                d.m.ldc2 = n;
+                ds.push_back(d);
                 if (j > 0) {
                     GemmArgs gr = garg(bq, j, bq + nr, Cbar, n, L + (int64_t)j * n, n, Lb + (int64_t)j * n, n);
                     gr.Ahead = M;
@@ -292,14 +405,9 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
                     add_tiles(rt, (int)ra.size() - 1, bq, j, false);
                 }
             }
-            B.diag(G_INV, inv);
             B.gemm(G_PANEL_A, pa, pt);
-            B.gemm(G_BBAR, ba, bt);
-            B.gemm(G_P, pp, ppt);
-            B.diag(G_WFORM, wf);
-            B.gemm(G_S, sa, st);
-            B.gemm(G_PANEL_A, tx, txt);
-            B.gemm(G_M, ma, mt);
+            B.gemm2(G_P_BBAR, pp, ppt, ba, bt);
+            if (!ds.empty()) B.ops.push_back({G_DSTEP, B.put(ds), (int64_t)ds.size(), 0});
             B.gemm(G_RBAR, ra, rt);
         }
         std::vector<GZero> z;
@@ -361,6 +469,8 @@ hipError_t grouped_enqueue(const GroupedSchedule* gp, hipStream_t s, int32_t* in
         case G_P: e = launch_gemm<double, true, false, EPI_STORE, false>(s, base, op); break;
         case G_S: e = launch_gemm<double, true, false, EPI_SYMLOW, false>(s, base, op); break;
         case G_M: e = launch_gemm<double, true, false, EPI_PHI, false>(s, base, op); break;
+        case G_P_BBAR: e = g.mixed ? launch_p_bbar<float>(s, base, op) : launch_p_bbar<double>(s, base, op); break;
+        case G_DSTEP: e = launch_dstep(s, base, op); break;
         case G_RBAR:
             e = g.mixed ? launch_gemm<float, true, false, EPI_SUB, false>(s, base, op)
                         : launch_gemm<double, true, false, EPI_SUB, false>(s, base, op);
@@ -377,6 +487,7 @@ void grouped_free(GroupedSchedule* g)
     if (!g) return;
     if (g->dbuf) (void)hipFree(g->dbuf);
     if (g->scratch) (void)hipFree(g->scratch);
+    if (g->invs) (void)hipFree(g->invs);
     delete g;
 }
 

@@ -122,6 +122,8 @@ int64_t gp_hypergrad_parts(int64_t n, int d);   // doubles of workspace for gp_h
 hipError_t gp_hypergrad_se(hipStream_t s, int64_t n, int d, const double* X, const double* theta, const double* Ab,
                            int64_t ldab, const double* scale, double* grad, double* part);
 hipError_t gp_value(hipStream_t s, int64_t n, const double* z, const double* logdet, double* f);
+// f = -1/2 a^T b - 1/2 logdet (fixed-order sum)
+hipError_t gp_value_dot(hipStream_t s, int64_t n, const double* a, const double* b, const double* logdet, double* f);
 int64_t symv_parts(int64_t n);                  // doubles of workspace for symv_lower
 // out = y + sgn * K x  (K symmetric from its lower triangle; absk: |K|; x null: ones; y null: 0)
 hipError_t symv_lower(hipStream_t s, int64_t n, const double* K, int64_t ldk, const double* x, int absk,

@@ -130,20 +130,32 @@ __global__ void __launch_bounds__(256) glm_fused_kernel(GlmArgs a)
     double lps = 0.0, das = 0.0;
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
     const int64_t r1 = min(a.n, r0 + a.rows_per_wg);
-    for (int64_t i = r0 + team; i < r1; i += TEAMS) {
+    // the next row of the team is loaded before the current one is used, so
+    // one row's loads are always in flight behind the arithmetic
+    double xn[V];
+    int32_t yn = 0;
+    auto load_row = [&](int64_t i) {
         const double* xr = a.X + i * a.ldx;
-        double x[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const int c = l + G * v;
-            x[v] = c < k ? xr[c] : 0.0;
+            xn[v] = (i < r1 && c < k) ? xr[c] : 0.0;
         }
+        yn = i < r1 ? a.y[i] : 0;
+    };
+    load_row(r0 + team);
+    for (int64_t i = r0 + team; i < r1; i += TEAMS) {
+        double x[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v] = xn[v];
+        const int32_t yi = yn;
+        load_row(i + TEAMS);
         double t = 0.0;
 #pragma unroll
         for (int v = 0; v < V; ++v) t += x[v] * s_beta[l + G * v];
         t = team_sum<G>(t, l);
         double lp, d;
-        glm_row(alpha + t, a.y[i], lp, d);
+        glm_row(alpha + t, yi, lp, d);
         lps += lp;
         das += d;
 #pragma unroll
@@ -241,26 +253,27 @@ __global__ void __launch_bounds__(256) glm_wide_xtd_kernel(GlmArgs a)
     }
 }
 
-// out[s] = sum over the nwg partial rows of slot s (fixed order): slot 0 ->
-// lp, 1 -> dalpha, 2 + c -> dbeta[c].
-__global__ void glm_reduce_kernel(int64_t nwg, int64_t k, const double* part, double* lp, double* dalpha,
-                                  double* dbeta)
+// out[s] = sum over the nwg partial rows of slot s = blockIdx.x (slot 0 ->
+// lp, 1 -> dalpha, 2 + c -> dbeta[c]): thread t adds rows t, t + 256, ...
+// in order, then a fixed tree over the 256 threads.
+__global__ void __launch_bounds__(256) glm_reduce_kernel(int64_t nwg, int64_t k, const double* part, double* lp,
+                                                         double* dalpha, double* dbeta)
 {
-    const int64_t sl = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (sl >= k + 2) return;
-    constexpr int G = 16;
+    __shared__ double red[256];
+    const int64_t sl = blockIdx.x;
     double s = 0.0;
-    for (int64_t w = 0; w < nwg; w += G) {
-        double v[G];
-#pragma unroll
-        for (int q = 0; q < G; ++q) v[q] = w + q < nwg ? part[(w + q) * (k + 2) + sl] : 0.0;
-#pragma unroll
-        for (int q = 0; q < G; ++q)
-            if (w + q < nwg) s += v[q];
+    for (int64_t w = threadIdx.x; w < nwg; w += 256) s += part[w * (k + 2) + sl];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
-    if (sl == 0) *lp = s;
-    else if (sl == 1) *dalpha = s;
-    else dbeta[sl - 2] = s;
+    if (threadIdx.x == 0) {
+        if (sl == 0) *lp = red[0];
+        else if (sl == 1) *dalpha = red[0];
+        else dbeta[sl - 2] = red[0];
+    }
 }
 
 template <int G, int V>
@@ -406,10 +419,11 @@ int64_t glm_workspace(int64_t n, int64_t k)
 
 int64_t glm_groups(int64_t n, int64_t k)
 {
-    // about 2^21 doubles of partial rows at most, 512 .. 16384 workgroups,
-    // never more than one per 4 rows
-    int64_t nwg = std::min<int64_t>(16384, std::max<int64_t>(512, (int64_t(1) << 21) / (k + 2)));
-    return std::max<int64_t>(1, std::min<int64_t>(nwg, (n + 3) / 4));
+    // 2048 workgroups (eight per CU) once there are 16 rows for each, fewer
+    // below; the partial rows (nwg x (k + 2) doubles) are then summed by one
+    // workgroup per slot
+    (void)k;
+    return std::max<int64_t>(1, std::min<int64_t>(2048, (n + 15) / 16));
 }
 
 hipError_t glm_bernoulli_logit(hipStream_t s, int64_t n, int64_t k, const double* X, int64_t ldx, const int32_t* y,
@@ -447,8 +461,7 @@ hipError_t glm_bernoulli_logit(hipStream_t s, int64_t n, int64_t k, const double
         }
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(glm_reduce_kernel, dim3((unsigned)((k + 2 + 255) / 256)), dim3(256), 0, s, nwg, k, ws, lp,
-                       dalpha, dbeta);
+    hipLaunchKernelGGL(glm_reduce_kernel, dim3((unsigned)(k + 2)), dim3(256), 0, s, nwg, k, ws, lp, dalpha, dbeta);
     return hipGetLastError();
 }
 

@@ -4,7 +4,10 @@ f(theta) = -1/2 y^T K^-1 y - 1/2 log|K|   (the constant -n/2 log 2 pi omitted)
 with K the squared-exponential ARD covariance of X plus noise,
 theta = (s2, l_1..l_d, sn2).  Forward: K -> factor L -> z, alpha, log|K| -> f.
 Backward: Lbar = tril(alpha z^T) - diag(1/L_ii) -> Abar (reverse-mode adjoint of
-the factor, section 3.3.2) -> df/dtheta.  Every step runs in the library's HIP
+the factor, section 3.3.2) -> df/dtheta.  In the mixed form (FP32 trailing
+updates) alpha comes from FP64 iterative refinement against K and
+z = L^T alpha, f = -1/2 y^T alpha - 1/2 log|K|: the data term and its
+gradient carry FP64 accuracy, the log-determinant term the mixed factor's.  Every step runs in the library's HIP
 kernels; this module only moves tensors between the calls.
 """
 from __future__ import annotations
@@ -56,7 +59,14 @@ class GPMarginalLogLik(torch.autograd.Function):
                 col = int(info.item())
             if col != 0:
                 raise NotPositiveDefiniteError(col)
-        f, z, alpha, _ = H.gp_value(L, y)
+        if precision == GPC_MIXED:
+            # alpha by FP64 refinement against the covariance (generated
+            # again: the factor overwrote the first copy), z = L^T alpha
+            K = H.gp_kgen_se(X, th)
+            f, z, alpha, _, _, _ = H.gp_value_refined(K, L, y, check=check)
+            del K
+        else:
+            f, z, alpha, _ = H.gp_value(L, y)
         if check:
             H.check()   # raises if a solve sweep ran out of time
         ctx.H, ctx.precision, ctx.recompute = H, precision, recompute_L

@@ -26,7 +26,7 @@ GPC_NOTRANS, GPC_TRANS = 0, 1
 EXPORTS = (
     "gpc_create", "gpc_destroy", "gpc_set_stream", "gpc_check", "gpc_set_options", "gpc_get_options",
     "gpc_factor", "gpc_factor_noalloc", "gpc_get_fallback", "gpc_adjoint", "gpc_trsm", "gpc_logdet",
-    "gpc_solve_refined", "gpc_gp_kgen_se", "gpc_gp_value", "gpc_gp_lbar", "gpc_gp_hypergrad_se",
+    "gpc_solve_refined", "gpc_gp_kgen_se", "gpc_gp_value", "gpc_gp_value_refined", "gpc_gp_lbar", "gpc_gp_hypergrad_se",
     "gpc_factor_batched", "gpc_adjoint_batched", "gpc_factor_adjoint_batched", "gpc_autotune_batched",
     "gpc_get_tuning",
     "gpc_trace_enable", "gpc_trace_reset", "gpc_trace_read",
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "gpc_solve_refined": [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
         "gpc_gp_kgen_se": [_vp, _i64, _i32, _vp, _vp, _vp, _i64],
         "gpc_gp_value": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp],
+        "gpc_gp_value_refined": [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
         "gpc_gp_lbar": [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i64],
         "gpc_gp_hypergrad_se": [_vp, _i64, _i32, _vp, _vp, _vp, _i64, _vp, _vp],
         "gpc_factor_batched": [_vp, _i32, _vp, _vp, _vp, _vp],
@@ -258,6 +259,23 @@ class Handle:
         self._check(self.lib.gpc_gp_value(self.h, n, _ptr(L), _mat(L, "L"), _ptr(y), _ptr(z), _ptr(alpha),
                                           _ptr(ld), _ptr(f)), "gpc_gp_value")
         return f, z, alpha, ld
+
+    def gp_value_refined(self, K: torch.Tensor, L: torch.Tensor, y: torch.Tensor, check: bool = True):
+        """(f, z, alpha, logdet, iters, eta) with alpha from FP64 refinement
+        against K and z = L^T alpha.  With check=False a refinement that did
+        not reach its tolerance still returns its outputs."""
+        n = L.shape[0]
+        z, alpha = torch.empty_like(y), torch.empty_like(y)
+        ld = torch.empty((), dtype=torch.float64, device=L.device)
+        f = torch.empty((), dtype=torch.float64, device=L.device)
+        iters = torch.empty((), dtype=torch.int32, device=L.device)
+        eta = torch.empty((), dtype=torch.float64, device=L.device)
+        self._sync_stream()
+        st = self.lib.gpc_gp_value_refined(self.h, n, _ptr(K), _mat(K, "K"), _ptr(L), _mat(L, "L"), _ptr(y),
+                                           _ptr(z), _ptr(alpha), _ptr(ld), _ptr(f), _ptr(iters), _ptr(eta))
+        if not (st == GPC_ERR_REFINE and not check):
+            self._check(st, "gpc_gp_value_refined")
+        return f, z, alpha, ld, iters, eta
 
     def gp_lbar(self, L: torch.Tensor, alpha: torch.Tensor, z: torch.Tensor, Lbar: torch.Tensor | None = None):
         n = L.shape[0]
