@@ -311,6 +311,8 @@ def main():
                     help="also trace one step with lookahead off (per-class kernel times, each kernel alone)")
     ap.add_argument("--headline-only", action="store_true")
     ap.add_argument("--no-ops", action="store_true", help="skip the operations beside the factor")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 512-matrix batch (for profiler runs; prints its own JSON line)")
     ap.add_argument("--mixed-only", action="store_true",
                     help="run only the mixed-form step (for profiler runs; prints its own JSON line)")
     args = ap.parse_args()
@@ -340,6 +342,26 @@ def main():
     H = Handle()
     H.set_options(block=args.block, precision=GPC_FP64, lookahead=args.lookahead)
     F = W.flops_factor(n) + W.flops_adjoint(n)
+
+    if args.batched_only:
+        # the batch alone, for profiler runs of its kernels (no headline)
+        del A0, Lb0, y0, L, Lb
+        torch.cuda.empty_cache()
+        bc = W.c4()
+        base0 = torch.from_numpy(bc["base"]).to(dev)
+        lbar0 = torch.from_numpy(bc["Lbar"]).to(dev)
+        bw, lw = torch.empty_like(base0), torch.empty_like(lbar0)
+        binfo = torch.zeros(len(bc["n"]), dtype=torch.int32, device=dev)
+        Hb = Handle()
+
+        def stepb():
+            bw.copy_(base0)
+            lw.copy_(lbar0)
+            Hb.factor_adjoint_batched(bc["n"], bc["off"], bw, lw, binfo)
+        msb = timed(stepb, args.steps, args.warmup, "batched")
+        print(json.dumps({"form": "batched", "workload": "se3d-batch512", "ms_per_step_with_copies": round(msb, 3)}),
+              flush=True)
+        return
 
     if args.mixed_only:
         # the mixed step alone, for profiler runs of its kernels (no headline)

@@ -1265,8 +1265,10 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
             GPC_HIP(h, hipMemcpy(p->d_tasks, tasks.data(), sizeof(gpc::BatchTask) * nb, hipMemcpyHostToDevice));
         }
         if (!h->cap_stream) GPC_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        if (schedule == 2 && !h->side) GPC_HIP(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
         GPC_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t le = schedule == 2 ? gpc::grouped_enqueue(p->grouped, h->cap_stream, info)
+        // the grouped schedule's zero fills become a parallel branch of the graph
+        hipError_t le = schedule == 2 ? gpc::grouped_enqueue(p->grouped, h->cap_stream, h->side, info)
                                       : gpc::batched_launch(h->cap_stream, nb, p->d_tasks, A, Lb, info, p->d_counter,
                                                             p->d_ws, p->wgs, mode);
         hipGraph_t g = nullptr;
@@ -1283,7 +1285,7 @@ gpc_status run_batched(gpc_handle* h, int mode, int32_t nb, const int32_t* n_hos
         // the caller is capturing: record the launch into its graph instead;
         // the plan's buffers then stay allocated until gpc_destroy
         p->pinned = true;
-        if (p->schedule == 2) GPC_HIP(h, gpc::grouped_enqueue(p->grouped, s, info));
+        if (p->schedule == 2) GPC_HIP(h, gpc::grouped_enqueue(p->grouped, s, nullptr, info));
         else GPC_HIP(h, gpc::batched_launch(s, nb, p->d_tasks, A, Lb, info, p->d_counter, p->d_ws, p->wgs, mode));
     }
     return GPC_OK;

@@ -26,21 +26,24 @@
 namespace gpc {
 namespace {
 
-constexpr int kGB = 64;   // block size of the grouped schedule
-constexpr int kGScr = 6;  // 64 x 64 scratch blocks per member (X, P, W, S, T, M)
+constexpr int kGB = 64;       // block size of the grouped schedule
+constexpr int kPSlices = 8;   // most k-slices of P = Cbar^T C per member
+// 64 x 64 scratch blocks per member: X, the slices of P, W, S, T, M
+constexpr int kScrX = 0, kScrP = 1, kScrW = kScrP + kPSlices, kScrS = kScrW + 1, kScrT = kScrS + 1,
+              kScrM = kScrT + 1, kGScr = kScrM + 1;
 
 struct GTile {
-    int32_t arg, tm, tn, pad;
+    int32_t arg, tm, tn, z;   // z: k-slice of a split product
 };
-struct GDiag {   // factor + inverse of a diagonal block / inverse alone / W = tril(Dbar - P)
+struct GDiag {   // factor + inverse of a diagonal block / inverse alone / W = tril(Dbar - sum of P slices)
     double* A;
-    const double* P;   // W step: P (nullptr: none)
+    const double* P;   // W step: the slices of P, kGB^2 apart (nullptr: none)
     double* X;         // inverse (factor, inverse) / W (W step)
     int32_t* info;
     int64_t lda;
     int64_t col0;
     int32_t kb;
-    int32_t pad;
+    int32_t np;        // W step: number of slices of P
 };
 struct GZero {
     double* A;
@@ -61,8 +64,8 @@ __global__ void __launch_bounds__(256) grouped_gemm_kernel(const GemmArgs* args,
 }
 
 // Two products of one block step in one launch: workgroups [0, n1) take the
-// tiles of list 1 (P = Cbar^T C, long inner dimension, so first), the rest
-// those of list 2 (Bbar -= Cbar R, FP64 or FP32 products).
+// tiles of list 1 (the k-slices of P = Cbar^T C, long inner dimension, so
+// first), the rest those of list 2 (Bbar -= Cbar R, FP64 or FP32 products).
 template <typename TU>
 __global__ void __launch_bounds__(256) grouped_p_bbar_kernel(const GemmArgs* a1, const GTile* t1, int n1,
                                                              const GemmArgs* a2, const GTile* t2)
@@ -74,7 +77,7 @@ __global__ void __launch_bounds__(256) grouped_p_bbar_kernel(const GemmArgs* a1,
     if (t < n1) {
         const GTile tt = t1[t];
         const GemmArgs g = a1[tt.arg];
-        gemm_tile<double, 64, 64, 16, 2, 2, true, false, EPI_STORE, false, double>(g, tt.tm, tt.tn, 0, lds);
+        gemm_tile<double, 64, 64, 16, 2, 2, true, false, EPI_PARTIAL, false, double>(g, tt.tm, tt.tn, tt.z, lds);
     } else {
         const GTile tt = t2[t - n1];
         const GemmArgs g = a2[tt.arg];
@@ -101,7 +104,11 @@ __global__ void __launch_bounds__(256) grouped_dstep_kernel(const GDStep* d)
         for (int e = threadIdx.x; e < kGB * kGB; e += 256) {
             const int r = e / kGB, c = e % kGB;
             double v = 0.0;
-            if (r < w.kb && c <= r) v = w.A[r * w.lda + c] - (w.P ? w.P[r * kGB + c] : 0.0);
+            if (r < w.kb && c <= r) {
+                double p = 0.0;
+                for (int z = 0; z < w.np; ++z) p += w.P[z * kGB * kGB + e];   // slices in order
+                v = w.A[r * w.lda + c] - p;
+            }
             w.X[e] = v;
         }
     }
@@ -138,19 +145,6 @@ __global__ void __launch_bounds__(256) grouped_inverse_kernel(const GDiag* d)
     diag_inverse<kGB / 16>(t.kb, t.A, t.lda, t.X, kGB, Ls, rowbuf);
 }
 
-// W = tril(Dbar - P) (P absent: tril(Dbar)), kb x kb, leading dimension kGB.
-__global__ void __launch_bounds__(256) grouped_wform_kernel(const GDiag* d)
-{
-    const GDiag t = d[blockIdx.x];
-    const int kb = t.kb;
-    for (int e = threadIdx.x; e < kGB * kGB; e += 256) {
-        const int r = e / kGB, c = e % kGB;
-        double v = 0.0;
-        if (r < kb && c <= r) v = t.A[r * t.lda + c] - (t.P ? t.P[r * kGB + c] : 0.0);
-        t.X[e] = v;
-    }
-}
-
 __global__ void grouped_info_kernel(int32_t* info, const int32_t* idx, int nb)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -167,17 +161,13 @@ __global__ void __launch_bounds__(256) grouped_zero_kernel(const GZero* z)
 }
 
 enum GOpKind : int {
-    G_INFO = 0, G_POTRF, G_INV, G_WFORM, G_ZERO,
+    G_INFO = 0, G_POTRF, G_INV, G_ZERO,
     G_PANEL_F,      // <double, MK, NK, STORE>            L21 = A21 X^T (in place)
     G_TRAIL,        // <TU, MK, NK, SUB, lower>           A22 -= L21 L21^T
-    G_PANEL_A,      // <double, MK, KN, STORE>            Cbar = Cbar X (in place); T = S X
-    G_BBAR,         // <TU, MK, KN, SUB>                  Bbar -= Cbar R
-    G_P,            // <double, KM, KN, STORE>            P = Cbar^T C
-    G_S,            // <double, KM, KN, SYMLOW>           S = sym(D^T W)
-    G_M,            // <double, KM, KN, PHI>              M = X^T T, Dbar <- Phi(M)
-    G_RBAR,         // <TU, KM, KN, SUB>                  Rbar -= [M; Cbar]^T [R; B]
-    G_P_BBAR,       // P = Cbar^T C and Bbar -= Cbar R in one launch
-    G_DSTEP         // W, S, T, M of the diagonal step, one workgroup per member
+    G_PANEL_A,      // <double, MK, KN, STORE>            Cbar = Cbar X (in place)
+    G_P_BBAR,       // slices of P = Cbar^T C, and Bbar -= Cbar R (TU), in one launch
+    G_DSTEP,        // W, S, T, M of the diagonal step, one workgroup per member
+    G_RBAR          // <TU, KM, KN, SUB>                  Rbar -= [M; Cbar]^T [R; B]
 };
 
 }  // namespace
@@ -198,6 +188,7 @@ struct GroupedSchedule {
     double* scratch = nullptr;
     double* invs = nullptr;   // inverses of every 64-block of every member (reverse sweep)
     bool mixed = false;
+    hipEvent_t fork = nullptr, join = nullptr;   // the zero-fill branch on a second stream
 };
 
 namespace {
@@ -307,6 +298,24 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
     std::vector<int32_t> idx(nb);
     for (int i = 0; i < nb; ++i) idx[i] = tasks[i].idx;
     const int64_t idx_off = B.put(idx);
+    // inverses of every 64-block of every member, for the reverse sweep: the
+    // factor's diagonal steps write them when both run in one call, else one
+    // launch forms them from L
+    std::vector<int64_t> inv0(nb);
+    int64_t nblk_all = 0;
+    for (int i = 0; i < nb; ++i) {
+        inv0[i] = nblk_all;
+        nblk_all += (tasks[i].n + kGB - 1) / kGB;
+    }
+    if (mode & 2) {
+        e = hipMalloc((void**)&g.invs, sizeof(double) * (size_t)std::max<int64_t>(1, nblk_all * kGB * kGB));
+        if (e != hipSuccess) {
+            *err = e;
+            grouped_free(gp);
+            return nullptr;
+        }
+    }
+    auto invp = [&](int i, int q) { return g.invs + (inv0[i] + q) * kGB * kGB; };
     if (mode & 1) {
         B.ops.push_back({G_INFO, idx_off, nb, 0});
         for (int s = 0; s < steps; ++s) {
@@ -318,11 +327,12 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
                 if (k >= n) continue;
                 const int kb = std::min(kGB, n - k);
                 double* A = Abase + tasks[i].off;
-                dg.push_back({A + (int64_t)k * n + k, nullptr, scr(i, 0), info + tasks[i].idx, n, k, kb, 0});
+                double* X = (mode & 2) ? invp(i, s) : scr(i, kScrX);
+                dg.push_back({A + (int64_t)k * n + k, nullptr, X, info + tasks[i].idx, n, k, kb, 0});
                 const int64_t m = n - k - kb;
                 if (m <= 0) continue;
                 double* A21 = A + (int64_t)(k + kb) * n + k;
-                pa.push_back(garg(m, kb, kb, A21, n, scr(i, 0), kGB, A21, n));
+                pa.push_back(garg(m, kb, kb, A21, n, X, kGB, A21, n));
                 add_tiles(pt, (int)pa.size() - 1, m, kb, false);
                 ta.push_back(garg(m, m, kb, A21, n, A21, n, A21 + kb, n));
                 add_tiles(tt, (int)ta.size() - 1, m, m, true);
@@ -337,30 +347,19 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
         if (!z.empty()) B.ops.push_back({G_ZERO, B.put(z), (int64_t)z.size(), 0});
     }
     if (mode & 2) {
-        // inverses of all diagonal blocks of all members, one launch up front
-        std::vector<int64_t> inv0(nb);
-        int64_t nblk_all = 0;
-        for (int i = 0; i < nb; ++i) {
-            inv0[i] = nblk_all;
-            nblk_all += (tasks[i].n + kGB - 1) / kGB;
-        }
-        e = hipMalloc((void**)&g.invs, sizeof(double) * (size_t)std::max<int64_t>(1, nblk_all * kGB * kGB));
-        if (e != hipSuccess) {
-            *err = e;
-            grouped_free(gp);
-            return nullptr;
-        }
-        auto invp = [&](int i, int q) { return g.invs + (inv0[i] + q) * kGB * kGB; };
-        std::vector<GDiag> inv;
-        for (int i = 0; i < nb; ++i) {
-            const int n = tasks[i].n;
-            const double* L = Abase + tasks[i].off;
-            for (int q = 0; q * kGB < n; ++q) {
-                const int j = q * kGB, bq = std::min(kGB, n - j);
-                inv.push_back({const_cast<double*>(L + (int64_t)j * n + j), nullptr, invp(i, q), nullptr, n, 0, bq, 0});
+        if (!(mode & 1)) {   // inverses of all diagonal blocks of all members, one launch up front
+            std::vector<GDiag> inv;
+            for (int i = 0; i < nb; ++i) {
+                const int n = tasks[i].n;
+                const double* L = Abase + tasks[i].off;
+                for (int q = 0; q * kGB < n; ++q) {
+                    const int j = q * kGB, bq = std::min(kGB, n - j);
+                    inv.push_back(
+                        {const_cast<double*>(L + (int64_t)j * n + j), nullptr, invp(i, q), nullptr, n, 0, bq, 0});
+                }
             }
+            B.diag(G_INV, inv);
         }
-        B.diag(G_INV, inv);
         for (int s = 0; s < steps; ++s) {
             std::vector<GDStep> ds;
             std::vector<GemmArgs> pa, ba, pp, ra;
@@ -375,8 +374,11 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
                 const double* D = L + (int64_t)j * n + j;
                 double* Dbar = Lb + (int64_t)j * n + j;
                 double* Cbar = Lb + (int64_t)k * n + j;
-                double *X = invp(i, q), *P = scr(i, 1), *W = scr(i, 2), *S = scr(i, 3), *T = scr(i, 4),
-                       *M = scr(i, 5);
+                double *X = invp(i, q), *P = scr(i, kScrP), *W = scr(i, kScrW), *S = scr(i, kScrS),
+                       *T = scr(i, kScrT), *M = scr(i, kScrM);
+                // P = Cbar^T C: its inner dimension nr split into slices of at
+                // least 128 (at most kPSlices), summed in order by the W step
+                const int np = nr > 0 ? (int)std::min<int64_t>(kPSlices, std::max<int64_t>(1, nr / 128)) : 0;
                 if (nr > 0) {
                     pa.push_back(garg(nr, bq, bq, Cbar, n, X, kGB, Cbar, n));
                     add_tiles(pt, (int)pa.size() - 1, nr, bq, false);
@@ -384,11 +386,14 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
                         ba.push_back(garg(nr, j, bq, Cbar, n, L + (int64_t)j * n, n, Lb + (int64_t)k * n, n));
                         add_tiles(bt, (int)ba.size() - 1, nr, j, false);
                     }
-                    pp.push_back(garg(bq, bq, nr, Cbar, n, L + (int64_t)k * n + j, n, P, kGB));
-                    add_tiles(ppt, (int)pp.size() - 1, bq, bq, false);
+                    GemmArgs gp = garg(bq, bq, nr, Cbar, n, L + (int64_t)k * n + j, n, P, kGB);
+                    gp.kchunk = ((nr + np - 1) / np + 15) / 16 * 16;
+                    gp.pstride = kGB * kGB;
+                    pp.push_back(gp);
+                    for (int z = 0; z * gp.kchunk < nr; ++z) ppt.push_back({(int)pp.size() - 1, 0, 0, z});
                 }
                 GDStep d{};
-                d.w = {Dbar, nr > 0 ? P : nullptr, W, nullptr, n, 0, bq, 0};
+                d.w = {Dbar, P, W, nullptr, n, 0, bq, nr > 0 ? (int)((nr + pp.back().kchunk - 1) / pp.back().kchunk) : 0};
                 d.s = garg(bq, bq, bq, D, n, W, kGB, S, kGB);
                 d.s.a_lower = 1;
                 d.t = garg(bq, bq, bq, S, kGB, X, kGB, T, kGB);
@@ -415,7 +420,9 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
             if (tasks[i].n > 1) z.push_back({Lbbase + tasks[i].off, tasks[i].n});
         if (!z.empty()) B.ops.push_back({G_ZERO, B.put(z), (int64_t)z.size(), 0});
     }
-    e = hipMalloc(&g.dbuf, std::max<size_t>(256, B.bytes.size()));
+    e = hipEventCreateWithFlags(&g.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g.join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&g.dbuf, std::max<size_t>(256, B.bytes.size()));
     if (e == hipSuccess) e = hipMemcpy(g.dbuf, B.bytes.data(), B.bytes.size(), hipMemcpyHostToDevice);
     g.ops = std::move(B.ops);
     *err = e;
@@ -426,13 +433,30 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
     return gp;
 }
 
-hipError_t grouped_enqueue(const GroupedSchedule* gp, hipStream_t s, int32_t* info)
+// side: a second stream for the zero fills of the strict upper triangles,
+// which no other launch reads, so that they overlap the block steps (the
+// branch forks from s at the start and joins it at the end); nullptr: all on s.
+hipError_t grouped_enqueue(const GroupedSchedule* gp, hipStream_t s, hipStream_t side, int32_t* info)
 {
     const GroupedSchedule& g = *gp;
     const unsigned char* base = (const unsigned char*)g.dbuf;
+    const bool fork = side && g.fork && g.join;
+    if (fork) {
+        hipError_t e = hipEventRecord(g.fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, g.fork, 0);
+        for (const GroupedOp& op : g.ops) {
+            if (op.kind != G_ZERO || e != hipSuccess) continue;
+            hipLaunchKernelGGL(grouped_zero_kernel, dim3((unsigned)op.count, 16), dim3(256), 0, side,
+                               (const GZero*)(base + op.off));
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(g.join, side);
+        if (e != hipSuccess) return e;
+    }
     for (const GroupedOp& op : g.ops) {
         hipError_t e = hipSuccess;
         const dim3 grid((unsigned)op.count);
+        if (fork && op.kind == G_ZERO) continue;
         switch (op.kind) {
         case G_INFO:
             hipLaunchKernelGGL(grouped_info_kernel, dim3((unsigned)((op.count + 255) / 256)), dim3(256), 0, s, info,
@@ -447,10 +471,6 @@ hipError_t grouped_enqueue(const GroupedSchedule* gp, hipStream_t s, int32_t* in
             hipLaunchKernelGGL(grouped_inverse_kernel, grid, dim3(256), 0, s, (const GDiag*)(base + op.off));
             e = hipGetLastError();
             break;
-        case G_WFORM:
-            hipLaunchKernelGGL(grouped_wform_kernel, grid, dim3(256), 0, s, (const GDiag*)(base + op.off));
-            e = hipGetLastError();
-            break;
         case G_ZERO:
             hipLaunchKernelGGL(grouped_zero_kernel, dim3((unsigned)op.count, 16), dim3(256), 0, s,
                                (const GZero*)(base + op.off));
@@ -462,13 +482,6 @@ hipError_t grouped_enqueue(const GroupedSchedule* gp, hipStream_t s, int32_t* in
                         : launch_gemm<double, false, true, EPI_SUB, true>(s, base, op);
             break;
         case G_PANEL_A: e = launch_gemm<double, false, false, EPI_STORE, false>(s, base, op); break;
-        case G_BBAR:
-            e = g.mixed ? launch_gemm<float, false, false, EPI_SUB, false>(s, base, op)
-                        : launch_gemm<double, false, false, EPI_SUB, false>(s, base, op);
-            break;
-        case G_P: e = launch_gemm<double, true, false, EPI_STORE, false>(s, base, op); break;
-        case G_S: e = launch_gemm<double, true, false, EPI_SYMLOW, false>(s, base, op); break;
-        case G_M: e = launch_gemm<double, true, false, EPI_PHI, false>(s, base, op); break;
         case G_P_BBAR: e = g.mixed ? launch_p_bbar<float>(s, base, op) : launch_p_bbar<double>(s, base, op); break;
         case G_DSTEP: e = launch_dstep(s, base, op); break;
         case G_RBAR:
@@ -479,7 +492,7 @@ hipError_t grouped_enqueue(const GroupedSchedule* gp, hipStream_t s, int32_t* in
         }
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return fork ? hipStreamWaitEvent(s, g.join, 0) : hipSuccess;
 }
 
 void grouped_free(GroupedSchedule* g)
@@ -488,6 +501,8 @@ void grouped_free(GroupedSchedule* g)
     if (g->dbuf) (void)hipFree(g->dbuf);
     if (g->scratch) (void)hipFree(g->scratch);
     if (g->invs) (void)hipFree(g->invs);
+    if (g->fork) (void)hipEventDestroy(g->fork);
+    if (g->join) (void)hipEventDestroy(g->join);
     delete g;
 }
 

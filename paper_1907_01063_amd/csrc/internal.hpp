@@ -189,7 +189,7 @@ hipError_t spd_test_fill(hipStream_t s, int64_t n, double* A, double* Lb, int64_
 struct GroupedSchedule;
 GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, double* Lbbase, int32_t* info,
                                  int mode, hipError_t* err);
-hipError_t grouped_enqueue(const GroupedSchedule* g, hipStream_t s, int32_t* info);
+hipError_t grouped_enqueue(const GroupedSchedule* g, hipStream_t s, hipStream_t side, int32_t* info);
 void grouped_free(GroupedSchedule* g);
 
 }  // namespace gpc

@@ -439,16 +439,19 @@ hipError_t glm_bernoulli_logit(hipStream_t s, int64_t n, int64_t k, const double
     a.rows_per_wg = (n + nwg - 1) / nwg;
     hipError_t e = hipSuccess;
     if (k <= kGlmFusedMaxK) {
+        // teams of at most 16 lanes up to k = 128 (so that a wave works on
+        // four or more rows at once and the per-row likelihood terms are
+        // shared by few lanes), wider teams for wider rows
         if (k <= 1) e = glm_fused_launch<1, 1>(s, a, nwg);
         else if (k <= 2) e = glm_fused_launch<2, 1>(s, a, nwg);
         else if (k <= 4) e = glm_fused_launch<4, 1>(s, a, nwg);
         else if (k <= 8) e = glm_fused_launch<8, 1>(s, a, nwg);
         else if (k <= 16) e = glm_fused_launch<16, 1>(s, a, nwg);
-        else if (k <= 32) e = glm_fused_launch<32, 1>(s, a, nwg);
-        else if (k <= 64) e = glm_fused_launch<64, 1>(s, a, nwg);
-        else if (k <= 128) e = glm_fused_launch<64, 2>(s, a, nwg);
-        else if (k <= 256) e = glm_fused_launch<64, 4>(s, a, nwg);
-        else if (k <= 512) e = glm_fused_launch<64, 8>(s, a, nwg);
+        else if (k <= 32) e = glm_fused_launch<16, 2>(s, a, nwg);
+        else if (k <= 64) e = glm_fused_launch<16, 4>(s, a, nwg);
+        else if (k <= 128) e = glm_fused_launch<16, 8>(s, a, nwg);
+        else if (k <= 256) e = glm_fused_launch<32, 8>(s, a, nwg);
+        else if (k <= 512) e = glm_fused_launch<32, 16>(s, a, nwg);
         else if (k <= 1024) e = glm_fused_launch<64, 16>(s, a, nwg);
         else e = glm_fused_launch<64, 32>(s, a, nwg);
     } else {

@@ -122,3 +122,40 @@ def test_mixed_mll_gradient_error_budget(H):
     ef, eg = abs(float(host(f)) - fo) / abs(fo), relf(host(theta.grad), go)
     say(f"mixed mll: f err {ef:.2e}, grad err {eg:.2e}")
     assert ef <= 1e-3 and eg <= 1e-2
+
+
+@pytest.mark.parametrize("n", [257, 1000])
+def test_gp_value_refined(H, n):
+    """gpc_gp_value_refined with a mixed-form factor: alpha reaches the
+    oracle's FP64 alpha (refined to eta <= 1e-15), z = L^T alpha for that L,
+    f = -1/2 y^T alpha - 1/2 logdet with the mixed factor's log-det; with an
+    FP64 factor it agrees with gpc_gp_value."""
+    from paper_1907_01063_amd import GPC_FP64, GPC_MIXED
+    d = 4
+    x, y, th = _inputs(n, d, 70 + n)
+    Ko = oracle.gp_kgen_se(x, th[0], th[1:1 + d], th[-1])
+    Lo, _ = oracle.potrf(Ko)
+    fo, zo, ao, ldo = oracle.gp_mll(Lo, y)
+    X, Y, T = dev(x), dev(y), dev(th)
+    H.set_options(precision=GPC_MIXED, refine_tol=1e-15)
+    try:
+        L = H.gp_kgen_se(X, T)
+        info = H.factor(L)
+        K = H.gp_kgen_se(X, T)
+        f, z, a, ld, it, eta = H.gp_value_refined(K, L, Y, check=False)
+        assert int(host(info)) == 0
+    finally:
+        H.set_options(precision=GPC_FP64, refine_tol=1e-12)
+    Lh, ah = host(L), host(a)
+    ea = relf(ah, ao)
+    say(f"gp value refined n={n}: iters {int(host(it))} eta {float(host(eta)):.2e} alpha {ea:.2e}")
+    assert float(host(eta)) <= 1e-14 and ea <= 1e-10
+    assert relf(host(z), Lh.T @ ah) <= 1e-13
+    ld_mixed = 2.0 * np.sum(np.log(np.diag(Lh)))
+    assert abs(float(host(ld)) - ld_mixed) <= 1e-12 * abs(ld_mixed)
+    assert abs(float(host(f)) - (-0.5 * y @ ah - 0.5 * ld_mixed)) <= 1e-12 * abs(fo)
+    # FP64 factor: the same pieces as gpc_gp_value
+    L64 = dev(Lo)
+    f2, z2, a2, ld2, _, _ = H.gp_value_refined(dev(Ko), L64, Y)
+    assert relf(host(a2), ao) <= TOL and relf(host(z2), zo) <= 1e-10
+    assert abs(float(host(f2)) - fo) <= 1e-10 * abs(fo)

@@ -147,7 +147,8 @@ def alpha_of(c):
     return torch.tensor(c["alpha"], dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("n,k", [(0, 5), (1, 1), (37, 3), (1000, 10), (5000, 100), (3000, 2048), (2000, 3000)])
+@pytest.mark.parametrize("n,k", [(0, 5), (1, 1), (37, 3), (1000, 10), (333, 31), (5000, 100), (4001, 300),
+                                 (777, 600), (3000, 2048), (2000, 3000)])
 def test_glm_parity(H, n, k):
     c = W.glm(n, k)
     lp, da, db, dX = ops().glm_bernoulli_logit(H, dev(c["X"]), dev(c["y"]), alpha_of(c), dev(c["beta"]),
