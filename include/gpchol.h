@@ -81,6 +81,10 @@ typedef struct {
                                  largest member has order >= 256, else persistent);
                                  1 = persistent (one workgroup per matrix, one launch);
                                  2 = grouped (every block step one launch over all members) */
+    int32_t adjoint_pair;  /* gpc_adjoint: 1 (default) = the B-bar updates of two consecutive
+                              reverse-sweep steps are applied as one product of inner dimension
+                              2b (b a multiple of 128); 0 = one product of inner dimension b
+                              per step */
 } gpc_options;
 
 typedef struct gpc_handle gpc_handle;

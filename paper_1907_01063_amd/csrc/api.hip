@@ -411,6 +411,7 @@ gpc_status gpc_create(gpc_handle** out, void* stream)
     h->opt.precision = GPC_FP64;
     h->opt.block = 0;
     h->opt.lookahead = 1;
+    h->opt.adjoint_pair = 1;
     h->opt.refine_maxit = 10;
     h->opt.refine_tol = 1e-12;
     h->opt.mixed_fallback = 0;
@@ -531,6 +532,7 @@ gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
     if (o->test_flags != 0 && o->test_flags != 1) return GPC_ERR_ARG;
     if (o->gemm_max_splits < 0 || o->gemm_max_splits > kGemmMaxSplits) return GPC_ERR_ARG;
     if (o->batched_schedule < 0 || o->batched_schedule > 2) return GPC_ERR_ARG;
+    if (o->adjoint_pair < 0 || o->adjoint_pair > 1) return GPC_ERR_ARG;
     h->opt = *o;
     return GPC_OK;
 }
@@ -782,9 +784,14 @@ gpc_status gpc_factor_noalloc(gpc_handle* h, int64_t n, double* A, int64_t lda, 
 //   main: wait big(q+2); chain(q); record chain(q); wait big(q+1); narrow(q)
 //   side: wait chain(q); big(q); record big(q)
 // chain(q) reads columns that big(q+1) does not write; narrow(q) writes
-// columns big(q+1) writes.  The FP32 copies of Cbar and M read by big(q) are
-// double-buffered by step parity (chain(q-2), the next writer of the same
-// buffer, waits for big(q)); narrow and big use separate slice buffers.
+// columns big(q+1) writes.  In a pair (q, q-1) big(q) holds only the Rbar
+// update and big(q-1) the Bbar update of both steps; the rules above still
+// order every access (Bbar's deferred columns are read by no step before
+// q-2).  The FP32 copies of M read by big(q) are double-buffered by step
+// parity and those of Cbar by group parity (the first chain of the group
+// after next, the next writer of the same buffer, waits for a big(q') with
+// q' no larger than the group's last step); narrow and big use separate
+// slice buffers.
 gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* Lbar,
                        int64_t ldlb)
 {
@@ -799,6 +806,21 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     const bool mixed = h->opt.precision == GPC_MIXED;
     const bool la = h->opt.lookahead != 0 && nblk > 2;
     auto tiles128 = [](int64_t M, int64_t N) { return ((M + 127) / 128) * ((N + 127) / 128); };
+    // Pairs of steps (q, q-1) for q = nblk-2, nblk-4, ... (q-1 >= 1): step q
+    // applies its Bbar update only to the next block's columns; step q-1
+    // applies both steps' updates to all other columns as one product of
+    // inner dimension 2b, so the big products run at K = 2b.  The first b
+    // rows of that product (row block q) take only step q-1's term: they stop
+    // at k = b (their k >= b operand would be the diagonal block Dbar_q).
+    const bool pairs = h->opt.adjoint_pair != 0 && b % 128 == 0;
+    auto deferred = [&](int64_t q) { return pairs && q >= 2 && q <= nblk - 2 && (nblk - 2 - q) % 2 == 0; };
+    // parity of the group (pair or single step) of each step: the FP32 panel
+    // copies of one group share a buffer, groups alternate between two
+    std::vector<uint8_t> gpar((size_t)nblk, 0);
+    for (int64_t q = nblk - 1, g = -1; q >= 0; --q) {
+        if (!(q + 1 <= nblk - 1 && deferred(q + 1))) ++g;
+        gpar[(size_t)q] = (uint8_t)(g & 1);
+    }
 
     // plan the split counts of every step to size the slice buffers
     int64_t prn_elems = 1, prb_elems = 1;
@@ -817,10 +839,13 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     const size_t n_dinv = (size_t)nblk * bb;
     const size_t n_pd = std::max((size_t)kMaxSd * bb, (size_t)nblk * kDiagMax * kDiagMax);
     const size_t n_dbl = n_dinv + n_pd + 5 * bb + (size_t)prn_elems + (size_t)prb_elems;
-    // mixed: FP32 copies of the strict lower triangle of L, and (two each) of
-    // the current Cbar panel and of M: the FP32 operands of the updates
-    const int64_t ldf = n;
-    const size_t n_flt = mixed ? (size_t)n * n + 2 * (size_t)n * b + 2 * bb : 0;
+    // mixed: FP32 copies of the strict lower triangle of L, of the Cbar
+    // panels (two buffers of n x 2b: a pair's lower step in columns [0, b)
+    // from row 0, its upper step in columns [b, 2b) from row b, both rows
+    // counted from the lower step's first Cbar row) and (two) of M: the FP32
+    // operands of the updates
+    const int64_t ldf = n, ldcp = 2 * (int64_t)b;
+    const size_t n_flt = mixed ? (size_t)n * n + 4 * (size_t)n * b + 2 * bb : 0;
     gpc_status st = ensure_ws(h, sizeof(double) * n_dbl + sizeof(float) * n_flt);
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
@@ -833,7 +858,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     double* Prb = Prn + prn_elems;
     float* Lf = (float*)(Prb + prb_elems);
     float* Cf2 = Lf + (size_t)n * n;
-    float* Mf2 = Cf2 + 2 * (size_t)n * b;
+    float* Mf2 = Cf2 + 4 * (size_t)n * b;
     if (mixed) GPC_HIP(h, convert_lower_f32(s, n, L, ldl, Lf, ldf));
 
     {
@@ -861,7 +886,9 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         double* Cbar = Lbar + k * ldlb + j;
         const double* C = L + k * ldl + j;
         double* Mw = Mw2 + (q & 1) * bb;
-        float* Cf = Cf2 + (q & 1) * (size_t)n * b;
+        const bool defer = deferred(q), merge = q + 1 <= nblk - 1 && deferred(q + 1);
+        float* Cfp = Cf2 + gpar[(size_t)q] * (size_t)n * ldcp;      // the group's panel buffer
+        float* Cf = defer ? Cfp + (size_t)b * ldcp + b : Cfp;
         float* Mf = Mf2 + (q & 1) * bb;
         const double dbq = (double)bq, dnr = (double)nr;
         if (la && q + 2 <= nblk - 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(q + 2), 0));
@@ -876,7 +903,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
                 GemmArgs g5 = gemm_args(nr, hb, bq, Cbar, ldlb, Dq_inv, b, Cbar, ldlb);
                 if (mixed) {
                     g5.Cf = Cf;
-                    g5.ldcf = b;
+                    g5.ldcf = ldcp;
                 }
                 GPC_HIP(h, gemm_f64(s, panel_tile(nr, h->cus), false, false, EPI_STORE, false, g5, 1));
                 if (bq > hb) {
@@ -884,7 +911,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
                                              Cbar + hb, ldlb);
                     if (mixed) {
                         g5b.Cf = Cf + hb;
-                        g5b.ldcf = b;
+                        g5b.ldcf = ldcp;
                     }
                     GPC_HIP(h, gemm_f64(s, panel_tile(nr, h->cus), false, false, EPI_STORE, false, g5b, 1));
                 }
@@ -924,18 +951,22 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         if (j == 0) continue;
         // ---- updates of Bbar and Rbar, columns [c0, c0 + nc)
         const int64_t K = bq + nr;
+        // merge: this step's update and the deferred one of step q+1 (Cbar
+        // columns [j, j+2b) against L rows [j, j+2b))
         auto left = [&](hipStream_t qs, int64_t c0, int64_t nc) -> gpc_status {
             if (nr <= 0 || nc <= 0) return GPC_OK;
-            const double dnc = (double)nc;
-            Traced t(h, GPC_K_ADJ_LEFT_UPDATE, 2.0 * dnr * dnc * dbq,
-                     16.0 * dnr * dnc + (mixed ? 4.0 : 8.0) * (dnr * dbq + dbq * dnc), qs);
-            if (mixed) {
-                GemmArgs g6 = gemm_args(nr, nc, bq, Cf, b, Lf + j * ldf + c0, ldf, Lbar + k * ldlb + c0, ldlb);
-                GPC_HIP(h, gemm_f32in(qs, TILE_128, false, false, EPI_SUB, false, g6, 1));
-            } else {
-                GemmArgs g6 = gemm_args(nr, nc, bq, Cbar, ldlb, L + j * ldl + c0, ldl, Lbar + k * ldlb + c0, ldlb);
-                GPC_HIP(h, gemm_f64(qs, TILE_128, false, false, EPI_SUB, false, g6, 1));
+            const double dnc = (double)nc, kl = merge ? 2.0 * dbq : dbq;
+            const double flops = merge ? 2.0 * dnc * dbq * (2.0 * dnr - dbq) : 2.0 * dnr * dnc * dbq;
+            Traced t(h, GPC_K_ADJ_LEFT_UPDATE, flops, 16.0 * dnr * dnc + (mixed ? 4.0 : 8.0) * kl * (dnr + dnc), qs);
+            const int64_t K6 = merge ? 2 * bq : bq;
+            GemmArgs g6 = mixed ? gemm_args(nr, nc, K6, Cf, ldcp, Lf + j * ldf + c0, ldf, Lbar + k * ldlb + c0, ldlb)
+                                : gemm_args(nr, nc, K6, Cbar, ldlb, L + j * ldl + c0, ldl, Lbar + k * ldlb + c0, ldlb);
+            if (merge) {
+                g6.short_m = bq;
+                g6.short_k = bq;
             }
+            if (mixed) GPC_HIP(h, gemm_f32in(qs, TILE_128, false, false, EPI_SUB, false, g6, 1));
+            else GPC_HIP(h, gemm_f64(qs, TILE_128, false, false, EPI_SUB, false, g6, 1));
             return GPC_OK;
         };
         auto rowupd = [&](hipStream_t qs, int64_t c0, int64_t nc, double* Pbuf) -> gpc_status {
@@ -947,7 +978,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
                 Traced t(h, GPC_K_ADJ_ROW_UPDATE, 2.0 * dbq * dnc * (double)K,
                          (mixed ? 4.0 : 8.0) * (double)K * (dbq + dnc) + 8.0 * sr * dbq * dnc, qs);
                 if (mixed) {
-                    GemmArgs gr = gemm_args(bq, nc, K, Cf, b, Lf + j * ldf + c0, ldf, Pbuf, nc);
+                    GemmArgs gr = gemm_args(bq, nc, K, Cf, ldcp, Lf + j * ldf + c0, ldf, Pbuf, nc);
                     gr.Ahead = Mf;
                     gr.ldah = bq;
                     gr.head_k = bq;
@@ -972,7 +1003,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         if (la) {
             GPC_HIP(h, hipEventRecord(ev_chain(q), s));
             GPC_HIP(h, hipStreamWaitEvent(s2, ev_chain(q), 0));
-            if ((st = left(s2, 0, jb)) != GPC_OK) return st;
+            if (!defer && (st = left(s2, 0, jb)) != GPC_OK) return st;
             if ((st = rowupd(s2, 0, jb, Prb)) != GPC_OK) return st;
             GPC_HIP(h, hipEventRecord(ev_big(q), s2));
             if (q + 1 <= nblk - 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(q + 1), 0));
@@ -980,7 +1011,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         if ((st = left(s, jb, bn)) != GPC_OK) return st;
         if ((st = rowupd(s, jb, bn, Prn)) != GPC_OK) return st;
         if (!la) {
-            if ((st = left(s, 0, jb)) != GPC_OK) return st;
+            if (!defer && (st = left(s, 0, jb)) != GPC_OK) return st;
             if ((st = rowupd(s, 0, jb, Prb)) != GPC_OK) return st;
         }
     }

@@ -3,6 +3,7 @@ public header declares, and rejects bad arguments before touching a device."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -73,10 +74,20 @@ def test_create_without_device_reports_no_device():
     assert not h.value
 
 
-def test_options_struct_layout():
-    # the binding's struct mirrors gpc_options: four int32, a double, three int32
-    o = gpchol.gpc_options()
-    assert ctypes.sizeof(o) == 40
-    assert gpchol.gpc_options.gemm_max_splits.offset == 32
-    assert gpchol.gpc_options.refine_tol.offset == 16
-    assert gpchol.gpc_options.mixed_fallback.offset == 24
+def test_options_struct_layout(tmp_path):
+    # the binding's struct mirrors gpc_options as the C compiler lays it out
+    # from the public header: size and every field's offset
+    fields = [f for f, _ in gpchol.gpc_options._fields_]
+    body = "\n".join(f'    printf("{f} %zu\\n", offsetof(gpc_options, {f}));' for f in fields)
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"gpchol.h\"\n"
+                   "int main(void) {\n    printf(\"size %zu\\n\", sizeof(gpc_options));\n" + body + "\n    return 0;\n}\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    assert int(got["size"]) == ctypes.sizeof(gpchol.gpc_options)
+    for f in fields:
+        assert int(got[f]) == getattr(gpchol.gpc_options, f).offset, f

@@ -257,6 +257,28 @@ def test_blocking_and_lookahead_variants(H, block, look, n):
     assert relf(Ag, Ao) <= TOL
 
 
+@pytest.mark.parametrize("pair,look", [(0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("n", [1000, 1100, 1537, 2048])
+def test_adjoint_step_pairs(H, pair, look, n):
+    """Bbar updates of two reverse-sweep steps applied as one product of inner
+    dimension 2b (adjoint_pair = 1) or one product per step (0), with and
+    without lookahead.  n spans an even and an odd number of 256-blocks, a
+    ragged last block of one row and none."""
+    rng = np.random.default_rng(900 + n)
+    _, L0 = W.spd_from_factor(rng, n)
+    Lb = W.lower_normal(rng, n)
+    say(f"adjoint pairs={pair} lookahead={look} n={n}")
+    H.set_options(adjoint_pair=pair, lookahead=look)
+    try:
+        Lbt = dev(with_upper_garbage(Lb, 3))
+        H.adjoint(dev(L0), Lbt)
+        Ag = host(Lbt)
+    finally:
+        H.set_options(adjoint_pair=1, lookahead=1)
+    assert np.all(np.triu(Ag, 1) == 0.0)
+    assert relf(Ag, oracle.potrf_adjoint(L0, Lb)) <= TOL
+
+
 def test_info_with_lookahead(H):
     # failure in a late outer step while the big updates run on the side stream
     A = W.c3(n=1300)["A"].copy()
