@@ -585,6 +585,11 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
     float* Pf2 = (float*)(Linv + n_linv);
     const int64_t steps = (n + B - 1) / B;
     const bool la = !linv_ext && h->opt.lookahead != 0 && steps > 2;
+    // with lookahead the main stream's launches (the diagonal chain and the
+    // narrow updates) run beside the big update: their waves raise their issue
+    // priority, so that a SIMD shared with the big update's waves issues theirs
+    // first
+    const int cp = la ? 1 : 0;
     hipStream_t s2 = s;
     if (la) {
         if (!h->side) GPC_HIP(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
@@ -610,7 +615,7 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
             const double dbh = (double)bh;
             {
                 Traced tr(h, GPC_K_DIAG_FACTOR, dbh * dbh * dbh / 3.0, 16.0 * dbh * dbh);
-                GPC_HIP(h, potrf_diag(s, bh, A + kh * lda + kh, lda, Linv, ib, info, kh));
+                GPC_HIP(h, potrf_diag(s, bh, A + kh * lda + kh, lda, Linv, ib, info, kh, cp));
             }
             const int64_t m = n - kh - bh;
             if (m <= 0) continue;
@@ -619,6 +624,7 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
             {
                 Traced tr(h, GPC_K_PANEL_SOLVE, dm * dbh * dbh, 8.0 * (2.0 * dm * dbh + dbh * dbh));
                 GemmArgs pg = gemm_args(m, bh, bh, P, lda, Linv, ib, P, lda);
+                pg.prio = cp;
                 if (mixed) {
                     pg.Cf = Pf + (kh + bh - k) * B + h0;
                     pg.ldcf = B;
@@ -635,10 +641,12 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
                     const float* Pr = Pf + (kh + bh - k) * B + h0;
                     GemmArgs ng = gemm_args(m, nh, bh, Pr, B, Pr, B, P + bh, lda);
                     ng.c_lower = 1;
+                    ng.prio = cp;
                     GPC_HIP(h, gemm_f32in(s, skinny_tile(m, nh), false, true, EPI_SUB, false, ng, 1));
                 } else {
                     GemmArgs ng = gemm_args(m, nh, bh, P, lda, P, lda, P + bh, lda);
                     ng.c_lower = 1;
+                    ng.prio = cp;
                     GPC_HIP(h, gemm_f64(s, skinny_tile(m, nh), false, true, EPI_SUB, false, ng, 1));
                 }
             }
@@ -678,10 +686,12 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
             if (mixed) {
                 GemmArgs ng = gemm_args(m2, nB, kB, Pr, B, Pr, B, Cn, lda);
                 ng.c_lower = 1;
+                ng.prio = cp;
                 GPC_HIP(h, gemm_f32in(s, skinny_tile(m2, nB), false, true, EPI_SUB, false, ng, 1));
             } else {
                 GemmArgs ng = gemm_args(m2, nB, kB, Pd, lda, Pd, lda, Cn, lda);
                 ng.c_lower = 1;
+                ng.prio = cp;
                 GPC_HIP(h, gemm_f64(s, skinny_tile(m2, nB), false, true, EPI_SUB, false, ng, 1));
             }
         }

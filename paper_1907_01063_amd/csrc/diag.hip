@@ -22,8 +22,9 @@ namespace {
 // fits on a CU beside a product kernel's workgroup.
 template <int NT>
 __global__ void __launch_bounds__(256, 2)
-potrf_tile_kernel(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info, int64_t col0)
+potrf_tile_kernel(int kb, double* A, int64_t lda, double* Linv, int64_t ldi, int32_t* info, int64_t col0, int prio)
 {
+    if (prio) __builtin_amdgcn_s_setprio(3);
     __shared__ double F[NT * 256], LU[256];
     diag_tile_factor_inverse<NT>(kb, A, lda, Linv, ldi, info, col0, F, LU);
 }
@@ -78,17 +79,17 @@ hipError_t fill_f64(hipStream_t s, int64_t count, double* p, double v)
 }
 
 hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Linv, int64_t ldi,
-                      int32_t* info, int64_t col0)
+                      int32_t* info, int64_t col0, int prio)
 {
     if (kb <= 0) return hipSuccess;
     if (kb > kDiagMax || lda > (int64_t(1) << 20)) return hipErrorInvalidValue;   // 31-bit row-band offsets
     if (kb <= 32)
-        hipLaunchKernelGGL(potrf_tile_kernel<2>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
+        hipLaunchKernelGGL(potrf_tile_kernel<2>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0, prio);
     else if (kb <= 64)
-        hipLaunchKernelGGL(potrf_tile_kernel<4>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0);
+        hipLaunchKernelGGL(potrf_tile_kernel<4>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info, col0, prio);
     else
         hipLaunchKernelGGL(potrf_tile_kernel<kDiagMax / 16>, dim3(1), dim3(256), 0, s, kb, A, lda, Linv, ldi, info,
-                           col0);
+                           col0, prio);
     return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ template <typename TI, int BM, int BN, int BK, int WM, int WN, bool AKM, bool BN
 __global__ void __launch_bounds__(WM * WN * 64) __attribute__((amdgpu_waves_per_eu(WM * WN == 8 ? 4 : 2)))
 gemm_kernel(GemmArgs g)
 {
+    if (g.prio) __builtin_amdgcn_s_setprio(2);
     __shared__ TI lds[TileLds<TI, BM, BN, BK>::elems];
     // Workgroups are dealt to the 8 XCDs round-robin (id mod 8).  Renumber so
     // that XCD x works on the x-th contiguous range of tiles: consecutive

@@ -45,6 +45,8 @@ struct GemmArgs {
     int32_t group;            // tile order: bands of `group` tile rows (0/1 = row by row); set by the launcher
     int64_t short_m, short_k; // output rows < short_m use only k < short_k (short_m = 0: all rows use K);
                               // short_m a multiple of the tile height
+    int32_t prio;             // nonzero: the waves raise their issue priority (s_setprio): a launch on
+                              // the critical path beside a long product
 };
 
 // TILE_64W: 64 x 128 tiles of 8 waves (twice the workgroups of TILE_128 for
@@ -63,7 +65,7 @@ hipError_t gemm_f32in(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi,
 // inverse (lower, kb x kb, leading dimension ldi, upper zeroed) to Linv, and
 // record the first failing pivot as info = col0 + j + 1 if info is still 0.
 hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Linv,
-                      int64_t ldi, int32_t* info, int64_t col0);
+                      int64_t ldi, int32_t* info, int64_t col0, int prio = 0);
 // Inverses of the diagonal blocks of L: block q covers rows/cols [q*b, min(n,(q+1)*b)),
 // its inverse goes to Dinv + q*b*b (leading dimension b, upper zeroed).
 hipError_t trtri_diag_batched(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl,
