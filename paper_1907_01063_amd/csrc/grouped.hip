@@ -6,8 +6,10 @@
 // the largest members set the makespan.  Here every step of the blocked
 // algorithms of section 3.3 is one launch over all members that still have
 // that step: the diagonal-block factor (one workgroup per member), the panel
-// product and the lower-tile trailing update (one workgroup per 64 x 64
-// output tile of every member); the reverse sweep likewise (diagonal inverse,
+// product and the trailing update (one workgroup per 64 x 64 output tile of
+// every member; steps in pairs, the first updating only the next block's
+// columns and the second the rest with both panels, inner dimension 128); the
+// reverse sweep likewise (diagonal inverse,
 // panel product, left update, the split products of the diagonal step, row
 // update).  Member i runs its own step s at launch step s: in the factor its
 // block s from the top, in the reverse sweep its block s from the bottom, so
@@ -163,7 +165,8 @@ __global__ void __launch_bounds__(256) grouped_zero_kernel(const GZero* z)
 enum GOpKind : int {
     G_INFO = 0, G_POTRF, G_INV, G_ZERO,
     G_PANEL_F,      // <double, MK, NK, STORE>            L21 = A21 X^T (in place)
-    G_TRAIL,        // <TU, MK, NK, SUB, lower>           A22 -= L21 L21^T
+    G_TRAIL,        // <TU, MK, NK, SUB, lower>           A22 -= L21 L21^T (both panels of a step pair)
+    G_NARROW,       // <TU, MK, NK, SUB>, C upper masked  next block's columns -= L21 L21^T
     G_PANEL_A,      // <double, MK, KN, STORE>            Cbar = Cbar X (in place)
     G_P_BBAR,       // slices of P = Cbar^T C, and Bbar -= Cbar R (TU), in one launch
     G_DSTEP,        // W, S, T, M of the diagonal step, one workgroup per member
@@ -189,6 +192,7 @@ struct GroupedSchedule {
     double* invs = nullptr;   // inverses of every 64-block of every member (reverse sweep)
     bool mixed = false;
     hipEvent_t fork = nullptr, join = nullptr;   // the zero-fill branch on a second stream
+    size_t fork_op = 0;                          // the branch forks before ops[fork_op]
 };
 
 namespace {
@@ -316,12 +320,21 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
         }
     }
     auto invp = [&](int i, int q) { return g.invs + (inv0[i] + q) * kGB * kGB; };
+    // the zero fills fork where the factor's last 8 steps begin (their
+    // launches are small, so the fills' writes crowd out little), else at
+    // the start
+    size_t fork_op = 0;
     if (mode & 1) {
         B.ops.push_back({G_INFO, idx_off, nb, 0});
+        // Steps in pairs (s even, s + 1): step s updates only block s+1's
+        // columns ("narrow"); step s+1 updates the rest with both panels,
+        // columns [k - 64, k + 64) of the rows below block s+1, as one
+        // product of inner dimension 128.
         for (int s = 0; s < steps; ++s) {
+            if (s == std::max(0, steps - 8)) fork_op = B.ops.size();
             std::vector<GDiag> dg;
-            std::vector<GemmArgs> pa, ta;
-            std::vector<GTile> pt, tt;
+            std::vector<GemmArgs> pa, ta, na;
+            std::vector<GTile> pt, tt, nt;
             for (int i = 0; i < nb; ++i) {
                 const int n = tasks[i].n, k = s * kGB;
                 if (k >= n) continue;
@@ -334,11 +347,20 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
                 double* A21 = A + (int64_t)(k + kb) * n + k;
                 pa.push_back(garg(m, kb, kb, A21, n, X, kGB, A21, n));
                 add_tiles(pt, (int)pa.size() - 1, m, kb, false);
-                ta.push_back(garg(m, m, kb, A21, n, A21, n, A21 + kb, n));
-                add_tiles(tt, (int)ta.size() - 1, m, m, true);
+                if (s % 2 == 0) {
+                    const int64_t nn = std::min<int64_t>(kGB, m);
+                    GemmArgs gn = garg(m, nn, kb, A21, n, A21, n, A21 + kb, n);
+                    gn.c_lower = 1;
+                    na.push_back(gn);
+                    add_tiles(nt, (int)na.size() - 1, m, nn, false);
+                } else {   // block s-1 is whole and precedes this one
+                    ta.push_back(garg(m, m, kGB + kb, A21 - kGB, n, A21 - kGB, n, A21 + kb, n));
+                    add_tiles(tt, (int)ta.size() - 1, m, m, true);
+                }
             }
             B.diag(G_POTRF, dg);
             B.gemm(G_PANEL_F, pa, pt);
+            B.gemm(G_NARROW, na, nt);
             B.gemm(G_TRAIL, ta, tt);
         }
         std::vector<GZero> z;
@@ -420,6 +442,7 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
             if (tasks[i].n > 1) z.push_back({Lbbase + tasks[i].off, tasks[i].n});
         if (!z.empty()) B.ops.push_back({G_ZERO, B.put(z), (int64_t)z.size(), 0});
     }
+    g.fork_op = fork_op < B.ops.size() ? fork_op : 0;
     e = hipEventCreateWithFlags(&g.fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&g.join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&g.dbuf, std::max<size_t>(256, B.bytes.size()));
@@ -434,27 +457,29 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
 }
 
 // side: a second stream for the zero fills of the strict upper triangles,
-// which no other launch reads, so that they overlap the block steps (the
-// branch forks from s at the start and joins it at the end); nullptr: all on s.
+// which no other launch reads or writes, so that they overlap the block steps
+// (the branch forks from s before ops[fork_op] and joins it at the end);
+// nullptr: all on s.
 hipError_t grouped_enqueue(const GroupedSchedule* gp, hipStream_t s, hipStream_t side, int32_t* info)
 {
     const GroupedSchedule& g = *gp;
     const unsigned char* base = (const unsigned char*)g.dbuf;
     const bool fork = side && g.fork && g.join;
-    if (fork) {
-        hipError_t e = hipEventRecord(g.fork, s);
-        if (e == hipSuccess) e = hipStreamWaitEvent(side, g.fork, 0);
-        for (const GroupedOp& op : g.ops) {
-            if (op.kind != G_ZERO || e != hipSuccess) continue;
-            hipLaunchKernelGGL(grouped_zero_kernel, dim3((unsigned)op.count, 16), dim3(256), 0, side,
-                               (const GZero*)(base + op.off));
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess) e = hipEventRecord(g.join, side);
-        if (e != hipSuccess) return e;
-    }
-    for (const GroupedOp& op : g.ops) {
+    for (size_t oi = 0; oi < g.ops.size(); ++oi) {
+        const GroupedOp& op = g.ops[oi];
         hipError_t e = hipSuccess;
+        if (fork && oi == g.fork_op) {
+            e = hipEventRecord(g.fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(side, g.fork, 0);
+            for (const GroupedOp& z : g.ops) {
+                if (z.kind != G_ZERO || e != hipSuccess) continue;
+                hipLaunchKernelGGL(grouped_zero_kernel, dim3((unsigned)z.count, 16), dim3(256), 0, side,
+                                   (const GZero*)(base + z.off));
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipEventRecord(g.join, side);
+            if (e != hipSuccess) return e;
+        }
         const dim3 grid((unsigned)op.count);
         if (fork && op.kind == G_ZERO) continue;
         switch (op.kind) {
@@ -480,6 +505,10 @@ hipError_t grouped_enqueue(const GroupedSchedule* gp, hipStream_t s, hipStream_t
         case G_TRAIL:
             e = g.mixed ? launch_gemm<float, false, true, EPI_SUB, true>(s, base, op)
                         : launch_gemm<double, false, true, EPI_SUB, true>(s, base, op);
+            break;
+        case G_NARROW:
+            e = g.mixed ? launch_gemm<float, false, true, EPI_SUB, false>(s, base, op)
+                        : launch_gemm<double, false, true, EPI_SUB, false>(s, base, op);
             break;
         case G_PANEL_A: e = launch_gemm<double, false, false, EPI_STORE, false>(s, base, op); break;
         case G_P_BBAR: e = g.mixed ? launch_p_bbar<float>(s, base, op) : launch_p_bbar<double>(s, base, op); break;

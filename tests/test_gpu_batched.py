@@ -73,6 +73,23 @@ def test_batched_parity(H):
         assert relf(Ag, Ao) <= TOL, k
 
 
+def test_batched_parity_long_members(H):
+    """Members of 10 to 16 block steps of 64: the grouped factor's step pairs
+    (odd and even step counts, ragged last blocks) and the zero fills forked
+    part-way through the factor, against the oracle per matrix."""
+    sizes = [1000, 700, 129, 1024, 641, 64]
+    As, Lbs = make_batch(7, sizes)
+    say("batched parity, long members")
+    Ls, Abs, info = run(H, As, Lbs, sizes)
+    assert np.all(info == 0)
+    for k, A, Lb, Lg, Ag in zip(sizes, As, Lbs, Ls, Abs):
+        Lo, _ = oracle.potrf(A)
+        Ao = oracle.potrf_adjoint(Lo, Lb)
+        assert np.all(np.triu(Lg, 1) == 0) and np.all(np.triu(Ag, 1) == 0)
+        assert relf(Lg, Lo) <= TOL, k
+        assert relf(Ag, Ao) <= TOL, k
+
+
 def test_batched_separate_calls_and_replay(H):
     As, Lbs = make_batch(2, SIZES[:8])
     a, off = pack(As)
