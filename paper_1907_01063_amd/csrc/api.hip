@@ -558,8 +558,9 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* o)
 //   side: wait panel(t); big(t); record big(t)
 // (panels(t) touch columns no big(t-1) writes; narrow(t) writes columns
 // big(t-1) writes; FP32 panel copies of the mixed form are double-buffered
-// by step parity, freed by the same waits.)  Then the strict upper triangle
-// is zeroed.
+// by step parity, freed by the same waits.)  The strict upper triangle is
+// zeroed: with lookahead on the side stream before its first big update,
+// else after the last step.
 namespace {
 
 // linv_ext: caller-provided room for the diagonal block's inverse (at least
@@ -598,6 +599,10 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
         if (!e0) return GPC_ERR_HIP;
         GPC_HIP(h, hipEventRecord(e0, s));
         GPC_HIP(h, hipStreamWaitEvent(s2, e0, 0));
+        // no launch of the factor reads the strict upper triangle, and none
+        // writes it but with zeros: clear it here on the side stream, beside
+        // the first diagonal steps, not after the last one
+        GPC_HIP(h, zero_strict_upper(s2, n, A, lda));
     }
     // events: 1 + 2t = panel(t), 2 + 2t = big(t)
     auto ev_panel = [&](int64_t t) { return sync_event(h, 1 + 2 * (size_t)t); };
@@ -705,7 +710,7 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
         GPC_HIP(h, hipEventRecord(ej, s2));
         GPC_HIP(h, hipStreamWaitEvent(s, ej, 0));
     }
-    GPC_HIP(h, zero_strict_upper(s, n, A, lda));
+    if (!la) GPC_HIP(h, zero_strict_upper(s, n, A, lda));
     return GPC_OK;
 }
 
@@ -884,6 +889,9 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         if (!e0 || !sync_event(h, 2 + 2 * (size_t)nblk)) return GPC_ERR_HIP;
         GPC_HIP(h, hipEventRecord(e0, s));
         GPC_HIP(h, hipStreamWaitEvent(s2, e0, 0));
+        // the sweep reads no element of Lbar's strict upper triangle and
+        // writes none but with zeros: clear it on the side stream at the start
+        GPC_HIP(h, zero_strict_upper(s2, n, Lbar, ldlb));
     }
     auto ev_chain = [&](int64_t q) { return sync_event(h, 1 + 2 * (size_t)q); };
     auto ev_big = [&](int64_t q) { return sync_event(h, 2 + 2 * (size_t)q); };
@@ -1029,8 +1037,9 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         hipEvent_t ej = sync_event(h, 0);
         GPC_HIP(h, hipEventRecord(ej, s2));
         GPC_HIP(h, hipStreamWaitEvent(s, ej, 0));
+    } else {
+        GPC_HIP(h, zero_strict_upper(s, n, Lbar, ldlb));
     }
-    GPC_HIP(h, zero_strict_upper(s, n, Lbar, ldlb));
     return GPC_OK;
 }
 
