@@ -276,7 +276,7 @@ def mixed_step(args, A0, Lb0, y0, info, ld):
     Lm, Lbm = torch.empty_like(A0), torch.empty_like(Lb0)
     xr = torch.empty_like(y0)
     Hm = Handle()
-    Hm.set_options(block=args.block, precision=GPC_MIXED, lookahead=args.lookahead, adjoint_pair=args.adjoint_pair)
+    Hm.set_options(block=args.block, precision=GPC_MIXED, lookahead=args.lookahead, adjoint_group=args.adjoint_group)
     out = {}
 
     def stepmix():
@@ -298,8 +298,8 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--lookahead", type=int, default=1)
-    ap.add_argument("--adjoint-pair", type=int, default=1, choices=[0, 1],
-                    help="B-bar updates of two reverse-sweep steps as one product (1) or one per step (0)")
+    ap.add_argument("--adjoint-group", type=int, default=0, choices=range(0, 9),
+                    help="reverse-sweep steps whose B-bar updates are applied together (0 = library default)")
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--gp-evals", type=int, default=10,
                     help="GP gradient evaluations timed per form (of the workload's 100 jittered thetas)")
@@ -342,7 +342,7 @@ def main():
     info = torch.zeros((), dtype=torch.int32, device=dev)
     ld = torch.zeros((), dtype=torch.float64, device=dev)
     H = Handle()
-    H.set_options(block=args.block, precision=GPC_FP64, lookahead=args.lookahead, adjoint_pair=args.adjoint_pair)
+    H.set_options(block=args.block, precision=GPC_FP64, lookahead=args.lookahead, adjoint_group=args.adjoint_group)
     F = W.flops_factor(n) + W.flops_adjoint(n)
 
     if args.batched_only:
@@ -454,7 +454,7 @@ def main():
 
     cfg = {"workload": f"matern32-2d-n{n} factor+solves+logdet+adjoint", "n": n, "form": "fp64",
            "factor_block": args.block or (512 if n >= 8192 else 256), "adjoint_block": min(args.block or 256, 256),
-           "lookahead": args.lookahead, "adjoint_pair": args.adjoint_pair, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
+           "lookahead": args.lookahead, "adjoint_group": args.adjoint_group or 2, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
            "factor_residual_sampled": res_fact, "solve_eta_inf": eta64}
 
     if not args.headline_only:

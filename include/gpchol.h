@@ -81,10 +81,10 @@ typedef struct {
                                  largest member has order >= 256, else persistent);
                                  1 = persistent (one workgroup per matrix, one launch);
                                  2 = grouped (every block step one launch over all members) */
-    int32_t adjoint_pair;  /* gpc_adjoint: 1 (default) = the B-bar updates of two consecutive
-                              reverse-sweep steps are applied as one product of inner dimension
-                              2b (b a multiple of 128); 0 = one product of inner dimension b
-                              per step */
+    int32_t adjoint_group; /* gpc_adjoint: the B-bar updates of G consecutive reverse-sweep
+                              steps are applied together, as products of inner dimension up to
+                              G b (b a multiple of 128); 0 = library default (2), 1 = one
+                              product of inner dimension b per step, 2..8 = G */
 } gpc_options;
 
 typedef struct gpc_handle gpc_handle;

@@ -109,6 +109,8 @@ namespace {
 using namespace gpc;
 
 constexpr int kDefaultBlock = 256;
+// Reverse-sweep steps whose Bbar updates are applied together (by default, at most)
+constexpr int kDefaultAdjGroup = 2, kMaxAdjGroup = 8;
 // Batched calls take the grouped schedule by default once a member is this large.
 constexpr int kGroupedMinN = 256;
 
@@ -411,7 +413,6 @@ gpc_status gpc_create(gpc_handle** out, void* stream)
     h->opt.precision = GPC_FP64;
     h->opt.block = 0;
     h->opt.lookahead = 1;
-    h->opt.adjoint_pair = 1;
     h->opt.refine_maxit = 10;
     h->opt.refine_tol = 1e-12;
     h->opt.mixed_fallback = 0;
@@ -532,7 +533,7 @@ gpc_status gpc_set_options(gpc_handle* h, const gpc_options* o)
     if (o->test_flags != 0 && o->test_flags != 1) return GPC_ERR_ARG;
     if (o->gemm_max_splits < 0 || o->gemm_max_splits > kGemmMaxSplits) return GPC_ERR_ARG;
     if (o->batched_schedule < 0 || o->batched_schedule > 2) return GPC_ERR_ARG;
-    if (o->adjoint_pair < 0 || o->adjoint_pair > 1) return GPC_ERR_ARG;
+    if (o->adjoint_group < 0 || o->adjoint_group > kMaxAdjGroup) return GPC_ERR_ARG;
     h->opt = *o;
     return GPC_OK;
 }
@@ -799,14 +800,15 @@ gpc_status gpc_factor_noalloc(gpc_handle* h, int64_t n, double* A, int64_t lda, 
 //   main: wait big(q+2); chain(q); record chain(q); wait big(q+1); narrow(q)
 //   side: wait chain(q); big(q); record big(q)
 // chain(q) reads columns that big(q+1) does not write; narrow(q) writes
-// columns big(q+1) writes.  In a pair (q, q-1) big(q) holds only the Rbar
-// update and big(q-1) the Bbar update of both steps; the rules above still
-// order every access (Bbar's deferred columns are read by no step before
-// q-2).  The FP32 copies of M read by big(q) are double-buffered by step
-// parity and those of Cbar by group parity (the first chain of the group
-// after next, the next writer of the same buffer, waits for a big(q') with
-// q' no larger than the group's last step); narrow and big use separate
-// slice buffers.
+// columns big(q+1) writes.  In a group of steps the earlier steps' big(q)
+// hold only their Rbar updates and the group's last step's big the Bbar
+// updates of all of them; the rules above still order every access (each
+// step's chain reads only its own block's columns, and its narrow launch
+// applies every term still pending for them).  The FP32 copies of M read by
+// big(q) are double-buffered by step parity and those of Cbar by group
+// parity (the first chain of the group after next, the next writer of the
+// same buffer, waits for a big(q') with q' no larger than the group's last
+// step); narrow and big use separate slice buffers.
 gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, double* Lbar,
                        int64_t ldlb)
 {
@@ -821,20 +823,25 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     const bool mixed = h->opt.precision == GPC_MIXED;
     const bool la = h->opt.lookahead != 0 && nblk > 2;
     auto tiles128 = [](int64_t M, int64_t N) { return ((M + 127) / 128) * ((N + 127) / 128); };
-    // Pairs of steps (q, q-1) for q = nblk-2, nblk-4, ... (q-1 >= 1): step q
-    // applies its Bbar update only to the next block's columns; step q-1
-    // applies both steps' updates to all other columns as one product of
-    // inner dimension 2b, so the big products run at K = 2b.  The first b
-    // rows of that product (row block q) take only step q-1's term: they stop
-    // at k = b (their k >= b operand would be the diagonal block Dbar_q).
-    const bool pairs = h->opt.adjoint_pair != 0 && b % 128 == 0;
-    auto deferred = [&](int64_t q) { return pairs && q >= 2 && q <= nblk - 2 && (nblk - 2 - q) % 2 == 0; };
-    // parity of the group (pair or single step) of each step: the FP32 panel
-    // copies of one group share a buffer, groups alternate between two
+    // Groups of G steps: q0 = nblk-2, nblk-2-G, ... down to q_lo = max(1,
+    // q0-G+1).  Step q of a group applies its Bbar update to the next block's
+    // columns together with the updates still pending from the group's
+    // earlier steps q+1 .. q0 (Cbar columns [j, j + P b) of Lbar against rows
+    // [j, j + P b) of L, P = q0 - q + 1); the group's last step applies all of
+    // them to the other columns too, so the big products run at K = G b.
+    // Row block r of such a product (counted from its first row) takes the
+    // terms of steps q .. q+r only: its k stops at (r+1) b, where the operand
+    // would run into the diagonal blocks and the strict upper triangle.
+    const int G = b % 128 == 0 ? (h->opt.adjoint_group > 0 ? h->opt.adjoint_group : kDefaultAdjGroup) : 1;
+    auto in_group = [&](int64_t q) { return q >= 1 && q <= nblk - 2; };
+    auto gtop = [&](int64_t q) { return q + (nblk - 2 - q) % G; };
+    auto glow = [&](int64_t q) { return std::max<int64_t>(1, gtop(q) - G + 1); };
+    // the FP32 panel copies of one group share a buffer; groups alternate
+    // between two (the last step, which has none, and step 0 count as groups)
     std::vector<uint8_t> gpar((size_t)nblk, 0);
-    for (int64_t q = nblk - 1, g = -1; q >= 0; --q) {
-        if (!(q + 1 <= nblk - 1 && deferred(q + 1))) ++g;
-        gpar[(size_t)q] = (uint8_t)(g & 1);
+    for (int64_t q = 0; q < nblk; ++q) {
+        const int64_t gi = in_group(q) ? (nblk - 2 - q) / G : (q == 0 ? (nblk - 2) / G + 1 : -1);
+        gpar[(size_t)q] = (uint8_t)(gi & 1);
     }
 
     // plan the split counts of every step to size the slice buffers
@@ -855,12 +862,11 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     const size_t n_pd = std::max((size_t)kMaxSd * bb, (size_t)nblk * kDiagMax * kDiagMax);
     const size_t n_dbl = n_dinv + n_pd + 5 * bb + (size_t)prn_elems + (size_t)prb_elems;
     // mixed: FP32 copies of the strict lower triangle of L, of the Cbar
-    // panels (two buffers of n x 2b: a pair's lower step in columns [0, b)
-    // from row 0, its upper step in columns [b, 2b) from row b, both rows
-    // counted from the lower step's first Cbar row) and (two) of M: the FP32
-    // operands of the updates
-    const int64_t ldf = n, ldcp = 2 * (int64_t)b;
-    const size_t n_flt = mixed ? (size_t)n * n + 4 * (size_t)n * b + 2 * bb : 0;
+    // panels (two buffers of n x G b: step q of a group whose last step is
+    // q_lo in columns and rows from (q - q_lo) b, rows counted from q_lo's
+    // first Cbar row) and (two) of M: the FP32 operands of the updates
+    const int64_t ldf = n, ldcp = (int64_t)G * b;
+    const size_t n_flt = mixed ? (size_t)n * n + 2 * (size_t)n * ldcp + 2 * bb : 0;
     gpc_status st = ensure_ws(h, sizeof(double) * n_dbl + sizeof(float) * n_flt);
     if (st != GPC_OK) return st;
     double* Dinv = (double*)h->ws;
@@ -873,7 +879,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     double* Prb = Prn + prn_elems;
     float* Lf = (float*)(Prb + prb_elems);
     float* Cf2 = Lf + (size_t)n * n;
-    float* Mf2 = Cf2 + 4 * (size_t)n * b;
+    float* Mf2 = Cf2 + 2 * (size_t)n * ldcp;
     if (mixed) GPC_HIP(h, convert_lower_f32(s, n, L, ldl, Lf, ldf));
 
     {
@@ -904,9 +910,11 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         double* Cbar = Lbar + k * ldlb + j;
         const double* C = L + k * ldl + j;
         double* Mw = Mw2 + (q & 1) * bb;
-        const bool defer = deferred(q), merge = q + 1 <= nblk - 1 && deferred(q + 1);
-        float* Cfp = Cf2 + gpar[(size_t)q] * (size_t)n * ldcp;      // the group's panel buffer
-        float* Cf = defer ? Cfp + (size_t)b * ldcp + b : Cfp;
+        const bool grp = in_group(q);
+        const int64_t P = grp ? gtop(q) - q + 1 : 1;          // steps whose Bbar terms this step applies
+        const bool defer = grp && q > glow(q);                // the group's later step applies the rest
+        const int64_t go = grp ? (q - glow(q)) * b : 0;       // this step's place in the group's buffer
+        float* Cf = Cf2 + gpar[(size_t)q] * (size_t)n * ldcp + (size_t)go * ldcp + go;
         float* Mf = Mf2 + (q & 1) * bb;
         const double dbq = (double)bq, dnr = (double)nr;
         if (la && q + 2 <= nblk - 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(q + 2), 0));
@@ -969,20 +977,20 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         if (j == 0) continue;
         // ---- updates of Bbar and Rbar, columns [c0, c0 + nc)
         const int64_t K = bq + nr;
-        // merge: this step's update and the deferred one of step q+1 (Cbar
-        // columns [j, j+2b) against L rows [j, j+2b))
+        // this step's Bbar term and the pending ones of steps q+1 .. q+P-1
+        // (Cbar columns [j, j + P b) against L rows [j, j + P b)), row block
+        // r of the product taking P' = min(P, r + 1) of them
         auto left = [&](hipStream_t qs, int64_t c0, int64_t nc) -> gpc_status {
             if (nr <= 0 || nc <= 0) return GPC_OK;
-            const double dnc = (double)nc, kl = merge ? 2.0 * dbq : dbq;
-            const double flops = merge ? 2.0 * dnc * dbq * (2.0 * dnr - dbq) : 2.0 * dnr * dnc * dbq;
-            Traced t(h, GPC_K_ADJ_LEFT_UPDATE, flops, 16.0 * dnr * dnc + (mixed ? 4.0 : 8.0) * kl * (dnr + dnc), qs);
-            const int64_t K6 = merge ? 2 * bq : bq;
+            const double dnc = (double)nc, dP = (double)P, kl = dP * dbq;
+            // k-products: (P-1) staircase row blocks, then the full ones
+            const double kprod = dbq * dbq * dP * (dP - 1.0) / 2.0 + (dnr - (dP - 1.0) * dbq) * dP * dbq;
+            Traced t(h, GPC_K_ADJ_LEFT_UPDATE, 2.0 * dnc * kprod,
+                     16.0 * dnr * dnc + (mixed ? 4.0 : 8.0) * kl * (dnr + dnc), qs);
+            const int64_t K6 = P * bq;
             GemmArgs g6 = mixed ? gemm_args(nr, nc, K6, Cf, ldcp, Lf + j * ldf + c0, ldf, Lbar + k * ldlb + c0, ldlb)
                                 : gemm_args(nr, nc, K6, Cbar, ldlb, L + j * ldl + c0, ldl, Lbar + k * ldlb + c0, ldlb);
-            if (merge) {
-                g6.short_m = bq;
-                g6.short_k = bq;
-            }
+            if (P > 1) g6.kstep = bq;
             if (mixed) GPC_HIP(h, gemm_f32in(qs, TILE_128, false, false, EPI_SUB, false, g6, 1));
             else GPC_HIP(h, gemm_f64(qs, TILE_128, false, false, EPI_SUB, false, g6, 1));
             return GPC_OK;

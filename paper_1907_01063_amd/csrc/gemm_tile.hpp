@@ -88,8 +88,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t tm, int64_t
 
     const int64_t m0 = tm * BM, n0 = tn * BN;
     const int64_t kbeg = z * g.kchunk;
-    // tile rows above short_m end their inner dimension at short_k (uniform per tile)
-    const int64_t kend = min(m0 < g.short_m ? min(g.K, g.short_k) : g.K, kbeg + g.kchunk);
+    // staircase: the tile's rows end their inner dimension at (m0 / kstep + 1) kstep (uniform per tile)
+    const int64_t kend = min(g.kstep > 0 ? min(g.K, (m0 / g.kstep + 1) * g.kstep) : g.K, kbeg + g.kchunk);
 
     // no __restrict__: the in-place panel products write the rows they read
     const TG* Ap = (const TG*)g.A;

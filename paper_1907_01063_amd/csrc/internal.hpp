@@ -43,8 +43,8 @@ struct GemmArgs {
     int64_t bsA, bsB, bsC;    // batch strides (elements) applied per blockIdx.y
     int32_t negate;           // EPI_STORE: store -acc
     int32_t group;            // tile order: bands of `group` tile rows (0/1 = row by row); set by the launcher
-    int64_t short_m, short_k; // output rows < short_m use only k < short_k (short_m = 0: all rows use K);
-                              // short_m a multiple of the tile height
+    int64_t kstep;            // > 0: output rows m use only k < (m / kstep + 1) kstep (a staircase);
+                              // kstep a multiple of the tile height
     int32_t prio;             // nonzero: the waves raise their issue priority (s_setprio): a launch on
                               // the critical path beside a long product
 };

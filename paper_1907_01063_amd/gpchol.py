@@ -50,7 +50,7 @@ class gpc_options(ctypes.Structure):
                 ("lookahead", ctypes.c_int32), ("refine_maxit", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("mixed_fallback", ctypes.c_int32),
                 ("test_flags", ctypes.c_int32), ("gemm_max_splits", ctypes.c_int32),
-                ("batched_schedule", ctypes.c_int32), ("adjoint_pair", ctypes.c_int32)]
+                ("batched_schedule", ctypes.c_int32), ("adjoint_group", ctypes.c_int32)]
 
 
 _i64, _i32, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p

@@ -106,24 +106,24 @@ def test_refined_solve_reports_nonconvergence(H):
         H.set_options(precision=0, refine_maxit=10, refine_tol=1e-12)
 
 
-@pytest.mark.parametrize("n,pair", [(400, 1), (1100, 0), (1100, 1)])
-def test_mixed_adjoint_given_factor_matches_fp64_closely(H, n, pair):
+@pytest.mark.parametrize("n,group", [(400, 0), (1100, 1), (1100, 2), (2600, 4)])
+def test_mixed_adjoint_given_factor_matches_fp64_closely(H, n, group):
     # the mixed adjoint only rounds its two trailing products to FP32; at
-    # n = 1100 (five 256-blocks) the Bbar updates of step pairs share one
-    # product when adjoint_pair is set
+    # n = 1100 (five 256-blocks) and 2600 (eleven) the Bbar updates of a group
+    # of steps share products whose FP32 panel copies share one buffer
     rng = np.random.default_rng(33)
     _, L0 = W.spd_from_factor(rng, n)
     Lb = W.lower_normal(rng, n)
     mixed(H)
-    H.set_options(adjoint_pair=pair)
+    H.set_options(adjoint_group=group)
     try:
         Lbt = dev(Lb)
         H.adjoint(dev(L0), Lbt)
     finally:
-        H.set_options(adjoint_pair=1)
+        H.set_options(adjoint_group=0)
         fp64(H)
     e = relf(host(Lbt), oracle.potrf_adjoint(L0, Lb))
-    say(f"mixed adjoint given factor n={n} pairs={pair}: {e:.2e}")
+    say(f"mixed adjoint given factor n={n} group={group}: {e:.2e}")
     assert e <= 1e-4
 
 

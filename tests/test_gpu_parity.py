@@ -257,24 +257,25 @@ def test_blocking_and_lookahead_variants(H, block, look, n):
     assert relf(Ag, Ao) <= TOL
 
 
-@pytest.mark.parametrize("pair,look", [(0, 1), (1, 0), (1, 1)])
-@pytest.mark.parametrize("n", [1000, 1100, 1537, 2048])
-def test_adjoint_step_pairs(H, pair, look, n):
-    """Bbar updates of two reverse-sweep steps applied as one product of inner
-    dimension 2b (adjoint_pair = 1) or one product per step (0), with and
-    without lookahead.  n spans an even and an odd number of 256-blocks, a
-    ragged last block of one row and none."""
+@pytest.mark.parametrize("group,look", [(1, 1), (2, 1), (3, 0), (3, 1), (4, 0), (4, 1), (8, 1)])
+@pytest.mark.parametrize("n", [1000, 1100, 1537, 2048, 2600])
+def test_adjoint_step_groups(H, group, look, n):
+    """Bbar updates of `group` reverse-sweep steps applied together (products
+    of inner dimension up to group x 256 with a staircase of k limits; 1 = one
+    product per step), with and without lookahead.  n spans 4 to 11
+    256-blocks, whole and partial groups, a ragged last block of one row and
+    none."""
     rng = np.random.default_rng(900 + n)
     _, L0 = W.spd_from_factor(rng, n)
     Lb = W.lower_normal(rng, n)
-    say(f"adjoint pairs={pair} lookahead={look} n={n}")
-    H.set_options(adjoint_pair=pair, lookahead=look)
+    say(f"adjoint group={group} lookahead={look} n={n}")
+    H.set_options(adjoint_group=group, lookahead=look)
     try:
         Lbt = dev(with_upper_garbage(Lb, 3))
         H.adjoint(dev(L0), Lbt)
         Ag = host(Lbt)
     finally:
-        H.set_options(adjoint_pair=1, lookahead=1)
+        H.set_options(adjoint_group=0, lookahead=1)
     assert np.all(np.triu(Ag, 1) == 0.0)
     assert relf(Ag, oracle.potrf_adjoint(L0, Lb)) <= TOL
 
