@@ -404,8 +404,22 @@ GroupedSchedule* grouped_prepare(int nb, const BatchTask* tasks, double* Abase, 
                 if (nr > 0) {
                     pa.push_back(garg(nr, bq, bq, Cbar, n, X, kGB, Cbar, n));
                     add_tiles(pt, (int)pa.size() - 1, nr, bq, false);
-                    if (j > 0) {
-                        ba.push_back(garg(nr, j, bq, Cbar, n, L + (int64_t)j * n, n, Lb + (int64_t)k * n, n));
+                    // Bbar -= Cbar R in pairs of the member's steps (q0, q0 - 1),
+                    // q0 = nblk-2, nblk-4, ...: step q0 updates only block
+                    // q0-1's columns, step q0-1 all columns with both terms
+                    // (inner dimension 128, its first row block stopping at 64)
+                    const bool ingrp = q >= 1 && q <= nblk - 2;
+                    const int top = ingrp ? q + (nblk - 2 - q) % 2 : q;
+                    const int terms = ingrp ? top - q + 1 : 1;
+                    const bool defer = ingrp && q > std::max(1, top - 1);
+                    if (defer) {
+                        ba.push_back(garg(nr, kGB, bq, Cbar, n, L + (int64_t)j * n + (j - kGB), n,
+                                          Lb + (int64_t)k * n + (j - kGB), n));
+                        add_tiles(bt, (int)ba.size() - 1, nr, kGB, false);
+                    } else if (j > 0) {
+                        GemmArgs gb = garg(nr, j, terms * bq, Cbar, n, L + (int64_t)j * n, n, Lb + (int64_t)k * n, n);
+                        if (terms > 1) gb.kstep = kGB;
+                        ba.push_back(gb);
                         add_tiles(bt, (int)ba.size() - 1, nr, j, false);
                     }
                     GemmArgs gp = garg(bq, bq, nr, Cbar, n, L + (int64_t)k * n + j, n, P, kGB);
