@@ -102,16 +102,28 @@ __global__ void __launch_bounds__(256) grouped_dstep_kernel(const GDStep* d)
     __shared__ double lds[TileLds<double, 64, 64, 16>::elems];
     const GDStep* t = d + blockIdx.x;
     {
+        // W = tril(Dbar - P): four elements per pass, all their slice loads
+        // issued before the (in-order) sums
         const GDiag w = t->w;
-        for (int e = threadIdx.x; e < kGB * kGB; e += 256) {
-            const int r = e / kGB, c = e % kGB;
-            double v = 0.0;
-            if (r < w.kb && c <= r) {
-                double p = 0.0;
-                for (int z = 0; z < w.np; ++z) p += w.P[z * kGB * kGB + e];   // slices in order
-                v = w.A[r * w.lda + c] - p;
+        for (int e0 = threadIdx.x; e0 < kGB * kGB; e0 += 4 * 256) {
+            double sl[4][kPSlices], d[4];
+            bool in[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 256, r = e / kGB, c = e % kGB;
+                in[u] = r < w.kb && c <= r;
+                d[u] = in[u] ? w.A[r * w.lda + c] : 0.0;
+#pragma unroll
+                for (int z = 0; z < kPSlices; ++z) sl[u][z] = in[u] && z < w.np ? w.P[z * kGB * kGB + e] : 0.0;
             }
-            w.X[e] = v;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                double p = 0.0;
+#pragma unroll
+                for (int z = 0; z < kPSlices; ++z)
+                    if (z < w.np) p += sl[u][z];   // slices in order
+                w.X[e0 + u * 256] = in[u] ? d[u] - p : 0.0;
+            }
         }
     }
     __syncthreads();
