@@ -60,3 +60,26 @@ def test_overlapping_outputs_rejected(H):
                                  it.data_ptr(), eta.data_ptr()) == GPC_ERR_ARG
     torch.cuda.synchronize()
     say("overlap checks ok")
+
+
+def test_options_out_of_range_rejected(H):
+    """gpc_set_options rejects every field outside its documented range with
+    GPC_ERR_ARG and keeps the previous options; the ends of each range are
+    accepted."""
+    from paper_1907_01063_amd.gpchol import GPC_ERR_ARG, GpcError
+    before = H.options()
+    bad = [("precision", 2), ("block", 100), ("block", 1024), ("refine_maxit", -1), ("refine_tol", 0.0),
+           ("mixed_fallback", 2), ("test_flags", 3), ("gemm_max_splits", -1), ("gemm_max_splits", 33),
+           ("batched_schedule", 3), ("adjoint_group", -1), ("adjoint_group", 9)]
+    for field, value in bad:
+        with pytest.raises(GpcError) as ei:
+            H.set_options(**{field: value})
+        assert ei.value.status == GPC_ERR_ARG, field
+        after = H.options()
+        assert all(getattr(after, f) == getattr(before, f) for f, _ in after._fields_), field
+    for field, value in [("adjoint_group", 8), ("adjoint_group", 1), ("adjoint_group", 0), ("block", 512),
+                         ("gemm_max_splits", 32), ("batched_schedule", 2)]:
+        H.set_options(**{field: value})
+        assert getattr(H.options(), field) == value
+    H.set_options(**{f: getattr(before, f) for f, _ in before._fields_})
+    say("option range checks ok")
