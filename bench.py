@@ -452,9 +452,12 @@ def main():
                 "serial_classes_ms": serial, "phases_ms": phases}
         log(f"trace: {json.dumps(roof)}")
 
+    # the library's defaults (include/gpchol.h, gpc_options.block and adjoint_group)
+    adj_block = min(args.block, 512) if args.block else (512 if n >= 8192 else 256)
+    adj_group = args.adjoint_group or (1 if adj_block >= 512 else 2)
     cfg = {"workload": f"matern32-2d-n{n} factor+solves+logdet+adjoint", "n": n, "form": "fp64",
-           "factor_block": args.block or (512 if n >= 8192 else 256), "adjoint_block": min(args.block or 256, 256),
-           "lookahead": args.lookahead, "adjoint_group": args.adjoint_group or 2, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
+           "factor_block": args.block or (512 if n >= 8192 else 256), "adjoint_block": adj_block,
+           "lookahead": args.lookahead, "adjoint_group": adj_group, "frac_of_fp64_peak": round(value / 1e3 / PEAK_TFLOPS["f64"], 4),
            "factor_residual_sampled": res_fact, "solve_eta_inf": eta64}
 
     if not args.headline_only:

@@ -62,8 +62,9 @@ typedef enum { GPC_NOTRANS = 0, GPC_TRANS = 1 } gpc_trans;
 typedef struct {
     int32_t precision;     /* gpc_precision; default GPC_FP64 */
     int32_t block;         /* outer block size b of the blocked algorithms; 0 = library default
-                              (factor: 512 in FP64 from n = 8192 up, else 256; the adjoint
-                              uses min(block, 256), 256 by default) */
+                              (factor: 512 in FP64 from n = 8192 up, else 256; adjoint: 512
+                              from n = 8192 up in both forms, else 256; the adjoint uses at
+                              most 512) */
     int32_t lookahead;     /* 1 = overlap the next diagonal step with the trailing update */
     int32_t refine_maxit;  /* maximum refinement iterations of gpc_solve_refined (default 10) */
     double  refine_tol;    /* stop when the normwise backward error eta_inf <= refine_tol (default 1e-12) */
@@ -83,7 +84,8 @@ typedef struct {
                                  2 = grouped (every block step one launch over all members) */
     int32_t adjoint_group; /* gpc_adjoint: the B-bar updates of G consecutive reverse-sweep
                               steps are applied together, as products of inner dimension up to
-                              G b (b a multiple of 128); 0 = library default (2), 1 = one
+                              G b (b a multiple of 128); 0 = library default (2 below
+                              512-blocks, else 1), 1 = one
                               product of inner dimension b per step, 2..8 = G */
 } gpc_options;
 

@@ -340,38 +340,47 @@ GemmArgs gemm_args(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, 
 
 }  // namespace
 
-// 256-blocks D = [[D1, 0], [D21, D2]]: D^-1 = [[X1, 0], [-X2 D21 X1, X2]],
-// X1 and X2 from the 128-block inverse kernel, the corner by two products.
+// b-blocks (b = 256 or 512) from the inverses of their 128-blocks, a level
+// at a time: a 2h-block D = [[D1, 0], [D21, D2]] with h-halves has
+// D^-1 = [[X1, 0], [-X2 D21 X1, X2]], its corner by two products batched over
+// the b-blocks that hold such a 2h-block at the same position (the last,
+// ragged b-block's with a shorter second half by two more).
 hipError_t gpc::diag_block_inverses(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl, double* Dinv,
                                     double* Tmp)
 {
     if (b <= kDiagMax) return trtri_diag_batched(s, n, b, L, ldl, Dinv);
-    if (b != 2 * kDiagMax) return hipErrorInvalidValue;
-    const int hb = kDiagMax;
+    if (b != 2 * kDiagMax && b != 4 * kDiagMax) return hipErrorInvalidValue;
     const int64_t nblk = (n + b - 1) / b, bb = (int64_t)b * b;
     hipError_t e = fill_f64(s, nblk * bb, Dinv, 0.0);
-    if (e == hipSuccess) e = trtri_diag_pairs(s, n, L, ldl, Dinv);
-    if (e == hipSuccess) e = fill_f64(s, nblk * (int64_t)hb * hb, Tmp, 0.0);
-    const int64_t nfull = n / b;
-    auto compose = [&](int64_t p0, int64_t cnt, int64_t m2) -> hipError_t {
+    if (e == hipSuccess) e = trtri_diag_into(s, n, b, L, ldl, Dinv);
+    // the 2h-blocks at position pos of b-blocks q0 .. q0+cnt-1, second half m2 rows
+    auto compose = [&](int64_t h, int64_t pos, int64_t q0, int64_t cnt, int64_t m2) -> hipError_t {
         if (cnt <= 0 || m2 <= 0) return hipSuccess;
-        const double* L21 = L + (p0 * b + hb) * ldl + p0 * b;
-        double* X1 = Dinv + p0 * bb;
-        double* T0 = Tmp + p0 * (int64_t)hb * hb;
-        GemmArgs g1 = gemm_args(m2, hb, hb, L21, ldl, X1, b, T0, hb);   // T0 = -D21 X1
+        const int64_t r0 = q0 * b + pos;
+        const double* L21 = L + (r0 + h) * ldl + r0;
+        double* X1 = Dinv + q0 * bb + pos * (b + 1);
+        double* T0 = Tmp;
+        GemmArgs g1 = gemm_args(m2, h, h, L21, ldl, X1, b, T0, h);   // T0 = -D21 X1
+        g1.negate = 1;
         g1.bsA = (int64_t)b * ldl + b;
         g1.bsB = bb;
-        g1.bsC = (int64_t)hb * hb;
-        hipError_t r = gemm_f64(s, TILE_128, false, false, EPI_SUB, false, g1, 1, (int)cnt);
+        g1.bsC = h * h;
+        hipError_t r = gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g1, 1, (int)cnt);
         if (r != hipSuccess) return r;
-        GemmArgs g2 = gemm_args(m2, hb, m2, X1 + (int64_t)hb * b + hb, b, T0, hb, X1 + (int64_t)hb * b, b);
+        GemmArgs g2 = gemm_args(m2, h, m2, X1 + h * b + h, b, T0, h, X1 + h * b, b);   // X21 = X2 T0
         g2.bsA = bb;
-        g2.bsB = (int64_t)hb * hb;
+        g2.bsB = h * h;
         g2.bsC = bb;
         return gemm_f64(s, TILE_128, false, false, EPI_STORE, false, g2, 1, (int)cnt);
     };
-    if (e == hipSuccess) e = compose(0, nfull, hb);
-    if (e == hipSuccess) e = compose(nfull, nblk - nfull, n - nfull * b - hb);   // ragged last block's second half
+    for (int64_t h = kDiagMax; h < b && e == hipSuccess; h *= 2) {
+        for (int64_t pos = 0; pos < b && e == hipSuccess; pos += 2 * h) {
+            // b-blocks whose 2h-block at pos has a whole second half, then the one with a partial one
+            const int64_t nfull = n >= pos + 2 * h ? (n - pos - 2 * h) / b + 1 : 0;
+            e = compose(h, pos, 0, std::min(nfull, nblk), h);
+            if (e == hipSuccess && nfull < nblk) e = compose(h, pos, nfull, 1, n - (nfull * b + pos + h));
+        }
+    }
     return e;
 }
 
@@ -817,7 +826,11 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     if (overlap(L, n, n, ldl, Lbar, n, n, ldlb)) return GPC_ERR_ARG;
     if (n == 0) return GPC_OK;
     hipStream_t s = h->stream;
-    const int b = std::min(block_of(h), kDefaultBlock);   // the adjoint's blocks stop at 256
+    // 512-blocks from n = 8192 in both forms (half the steps: taller row
+    // updates, fewer split-K slices and chain launches), else 256; an explicit
+    // block option up to 512
+    const int b = h->opt.block > 0 ? std::min(h->opt.block, 2 * kDefaultBlock)
+                                   : (n >= 8192 ? 2 * kDefaultBlock : kDefaultBlock);
     const int64_t nblk = (n + b - 1) / b;
     const int kMaxSd = 64, kMaxSr = 32;
     const bool mixed = h->opt.precision == GPC_MIXED;
@@ -832,7 +845,9 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     // Row block r of such a product (counted from its first row) takes the
     // terms of steps q .. q+r only: its k stops at (r+1) b, where the operand
     // would run into the diagonal blocks and the strict upper triangle.
-    const int G = b % 128 == 0 ? (h->opt.adjoint_group > 0 ? h->opt.adjoint_group : kDefaultAdjGroup) : 1;
+    // default: pairs below 512-blocks (the big products then run at K = 512)
+    const int G = b % 128 == 0 ? (h->opt.adjoint_group > 0 ? h->opt.adjoint_group : (b >= 512 ? 1 : kDefaultAdjGroup))
+                               : 1;
     auto in_group = [&](int64_t q) { return q >= 1 && q <= nblk - 2; };
     auto gtop = [&](int64_t q) { return q + (nblk - 2 - q) % G; };
     auto glow = [&](int64_t q) { return std::max<int64_t>(1, gtop(q) - G + 1); };
@@ -859,7 +874,7 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
     }
     const size_t bb = (size_t)b * b;
     const size_t n_dinv = (size_t)nblk * bb;
-    const size_t n_pd = std::max((size_t)kMaxSd * bb, (size_t)nblk * kDiagMax * kDiagMax);
+    const size_t n_pd = std::max((size_t)kMaxSd * bb, (size_t)nblk * (b / 2) * (b / 2));
     const size_t n_dbl = n_dinv + n_pd + 5 * bb + (size_t)prn_elems + (size_t)prb_elems;
     // mixed: FP32 copies of the strict lower triangle of L, of the Cbar
     // panels (two buffers of n x G b: step q of a group whose last step is
@@ -923,23 +938,17 @@ gpc_status gpc_adjoint(gpc_handle* h, int64_t n, const double* L, int64_t ldl, d
         if (nr > 0) {
             {
                 Traced t(h, GPC_K_ADJ_PANEL_SOLVE, dnr * dbq * dbq, 8.0 * (2.0 * dnr * dbq + dbq * dbq));
-                // Cbar <- Cbar D^-1 in place, 128 output columns per launch: the
-                // left columns first (they read the old right ones), then the right.
-                const int64_t hb = std::min<int64_t>(bq, kDiagMax);
-                GemmArgs g5 = gemm_args(nr, hb, bq, Cbar, ldlb, Dq_inv, b, Cbar, ldlb);
-                if (mixed) {
-                    g5.Cf = Cf;
-                    g5.ldcf = ldcp;
-                }
-                GPC_HIP(h, gemm_f64(s, panel_tile(nr, h->cus), false, false, EPI_STORE, false, g5, 1));
-                if (bq > hb) {
-                    GemmArgs g5b = gemm_args(nr, bq - hb, bq - hb, Cbar + hb, ldlb, Dq_inv + hb * b + hb, b,
-                                             Cbar + hb, ldlb);
+                // Cbar <- Cbar D^-1 in place, 128 output columns per launch from
+                // the left: output columns [c0, c0 + w) read the columns from c0
+                // on (D^-1 is lower), which no earlier launch has written.
+                for (int64_t c0 = 0; c0 < bq; c0 += kDiagMax) {
+                    const int64_t w = std::min<int64_t>(kDiagMax, bq - c0);
+                    GemmArgs g5 = gemm_args(nr, w, bq - c0, Cbar + c0, ldlb, Dq_inv + c0 * b + c0, b, Cbar + c0, ldlb);
                     if (mixed) {
-                        g5b.Cf = Cf + hb;
-                        g5b.ldcf = ldcp;
+                        g5.Cf = Cf + c0;
+                        g5.ldcf = ldcp;
                     }
-                    GPC_HIP(h, gemm_f64(s, panel_tile(nr, h->cus), false, false, EPI_STORE, false, g5b, 1));
+                    GPC_HIP(h, gemm_f64(s, panel_tile(nr, h->cus), false, false, EPI_STORE, false, g5, 1));
                 }
             }
             int64_t ch;

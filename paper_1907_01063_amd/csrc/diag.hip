@@ -41,18 +41,20 @@ trtri_batched_kernel(int64_t n, int b, const double* L, int64_t ldl, double* Din
     diag_inverse<kDiagMax / 16>(kb, L + r0 * ldl + r0, ldl, Dinv + (int64_t)blockIdx.x * b * b, b, Ls, rowbuf);
 }
 
-// Inverse of the kDiagMax-block p = blockIdx.x into the diagonal half
-// p & 1 of the 2 kDiagMax block p / 2 of Dinv (leading dimension 2 kDiagMax).
+// Inverse of the kDiagMax-block p = blockIdx.x into the diagonal of the
+// b-block p / (b / kDiagMax) of Dinv (leading dimension b), at its
+// (p mod (b / kDiagMax))-th kDiagMax position.
 __global__ void __launch_bounds__(256)
-trtri_pairs_kernel(int64_t n, const double* L, int64_t ldl, double* Dinv)
+trtri_into_kernel(int64_t n, int b, const double* L, int64_t ldl, double* Dinv)
 {
     __shared__ double Ls[kDiagMax * (kDiagMax + 1)];
     __shared__ double rowbuf[kDiagMax];
     const int64_t p = blockIdx.x;
     const int64_t r0 = p * kDiagMax;
     const int kb = (int)min((int64_t)kDiagMax, n - r0);
-    double* X = Dinv + (p >> 1) * (2 * kDiagMax) * (2 * kDiagMax) + (p & 1) * (kDiagMax * 2 * kDiagMax + kDiagMax);
-    diag_inverse<kDiagMax / 16>(kb, L + r0 * ldl + r0, ldl, X, 2 * kDiagMax, Ls, rowbuf);
+    const int per = b / kDiagMax;
+    double* X = Dinv + (p / per) * (int64_t)b * b + (p % per) * ((int64_t)kDiagMax * b + kDiagMax);
+    diag_inverse<kDiagMax / 16>(kb, L + r0 * ldl + r0, ldl, X, b, Ls, rowbuf);
 }
 
 __global__ void fill_f64_kernel(int64_t count, double* p, double v)
@@ -63,11 +65,12 @@ __global__ void fill_f64_kernel(int64_t count, double* p, double v)
 
 }  // namespace
 
-hipError_t trtri_diag_pairs(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Dinv)
+hipError_t trtri_diag_into(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl, double* Dinv)
 {
     if (n <= 0) return hipSuccess;
+    if (b < kDiagMax || b % kDiagMax != 0) return hipErrorInvalidValue;
     const int64_t nsub = (n + kDiagMax - 1) / kDiagMax;
-    hipLaunchKernelGGL(trtri_pairs_kernel, dim3((unsigned)nsub), dim3(256), 0, s, n, L, ldl, Dinv);
+    hipLaunchKernelGGL(trtri_into_kernel, dim3((unsigned)nsub), dim3(256), 0, s, n, b, L, ldl, Dinv);
     return hipGetLastError();
 }
 

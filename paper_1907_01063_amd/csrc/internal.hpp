@@ -70,14 +70,14 @@ hipError_t potrf_diag(hipStream_t s, int kb, double* A, int64_t lda, double* Lin
 // its inverse goes to Dinv + q*b*b (leading dimension b, upper zeroed).
 hipError_t trtri_diag_batched(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl,
                               double* Dinv);
-// Inverses of the 128-blocks of L written into the diagonal quadrants of
-// 256-blocks: sub-block p goes to Dinv + (p/2)*256*256 + (p%2)*(128*256+128),
-// leading dimension 256 (the rest of each 256-block is left untouched).
-hipError_t trtri_diag_pairs(hipStream_t s, int64_t n, const double* L, int64_t ldl, double* Dinv);
+// Inverses of the 128-blocks of L written onto the diagonals of b-blocks (b a
+// multiple of 128): sub-block p goes to Dinv + (p/per)*b*b + (p%per)*(128*b+128),
+// per = b/128, leading dimension b (the rest of each b-block is left untouched).
+hipError_t trtri_diag_into(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl, double* Dinv);
 hipError_t fill_f64(hipStream_t s, int64_t count, double* p, double v);
-// Inverses of the b x b diagonal blocks of L (b <= 128, or b = 256 composed
-// from the two 128 halves), lower with zero strict upper, at Dinv + q*b*b.
-// Tmp: ceil(n/b) * 128 * 128 doubles of scratch (b = 256 only).
+// Inverses of the b x b diagonal blocks of L (b <= 128, or b = 256 or 512
+// composed level by level from 128-block inverses), lower with zero strict
+// upper, at Dinv + q*b*b.  Tmp: ceil(n/b) * (b/2)^2 doubles of scratch (b > 128).
 hipError_t diag_block_inverses(hipStream_t s, int64_t n, int b, const double* L, int64_t ldl, double* Dinv,
                                double* Tmp);
 
