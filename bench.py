@@ -412,10 +412,12 @@ def main():
     roof = None
     if not args.no_trace:
         tr = tr_timed
-        # roofline kernel: the adjoint's left update Bbar -= Cbar R, the largest
-        # MFMA contraction of the step (its launches overlap the diagonal chain
-        # of the next block on the other stream, as in every timed step)
-        dom = "adj_left_update"
+        # roofline kernel: the adjoint's row update Rbar -= [M; Cbar]^T [R; B]
+        # (split-K slices), the class with the most time in the step's trace
+        # (33 ms against 31.5 for the left update Bbar -= Cbar R with
+        # 512-blocks); its launches overlap the diagonal chain of the next
+        # block on the other stream, as in every timed step
+        dom = "adj_row_update"
         cnt, kms, kfl, kby = tr[dom]
         achieved = kfl / (kms * 1e-3) / 1e12
         serial = None

@@ -73,9 +73,16 @@ int64_t group_bytes()
     return v;
 }
 
-template <typename TI, int BM>
+// A product of at most 16 tile rows and more than 8 tile columns walks its
+// tiles column by column (one band of all its rows): the tile rows of one
+// column, which share its column panel, then run together on one XCD, so
+// each column panel is read about once instead of once per tile row (each
+// XCD reads the few row panels, the larger operand once).
+template <typename TI, int BM, int BN, bool LOWER>
 int tile_group(const GemmArgs& g)
 {
+    const int64_t tilesM = (g.M + BM - 1) / BM, tilesN = (g.N + BN - 1) / BN;
+    if (!LOWER && group_bytes() > 0 && tilesM > 1 && tilesM <= 16 && tilesN > 8) return (int)tilesM;
     const int64_t kc = g.kchunk < g.K ? g.kchunk : g.K;
     const int64_t panel = (int64_t)BM * (kc > 0 ? kc : 1) * (int64_t)sizeof(TI);
     const int64_t G = group_bytes() / panel;
@@ -95,7 +102,7 @@ hipError_t launch(hipStream_t s, const GemmArgs& g, int splits, int batch)
     }
     dim3 grid((unsigned)tiles, (unsigned)(batch < 1 ? 1 : batch), (unsigned)(splits < 1 ? 1 : splits));
     GemmArgs ga = g;
-    ga.group = tile_group<TI, BM>(g);
+    ga.group = tile_group<TI, BM, BN, LOWER>(g);
     hipLaunchKernelGGL((gemm_kernel<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>), grid, dim3(WM * WN * 64), 0, s, ga);
     return hipGetLastError();
 }
