@@ -30,11 +30,19 @@ gemm_kernel(GemmArgs g)
 {
     if (g.prio) __builtin_amdgcn_s_setprio(2);
     __shared__ TI lds[TileLds<TI, BM, BN, BK>::elems];
-    // Workgroups are dealt to the 8 XCDs round-robin (id mod 8).  Renumber so
-    // that XCD x works on the x-th contiguous range of tiles: consecutive
-    // tiles share their row panel, which then stays in that XCD's L2.
-    const int nwg = gridDim.x, w = blockIdx.x, per = nwg / 8;
-    const int t = w < per * 8 ? (w % 8) * per + w / 8 : w;
+    // Workgroups are dealt to the 8 XCDs round-robin (dispatch id mod 8).
+    // Renumber so that XCD x works on the x-th contiguous range of tiles:
+    // consecutive tiles share their row panel, which then stays in that XCD's
+    // L2.  A split-K launch (slices along z) renumbers its (slice, tile)
+    // sequence as one, slice-major, so that an XCD takes whole slices and
+    // reads each slice's operand chunks alone, instead of every XCD reading
+    // the row panels of every slice.
+    const bool flat = gridDim.z > 1 && gridDim.y == 1;
+    const int nwg = flat ? gridDim.x * gridDim.z : gridDim.x;
+    const int w = flat ? blockIdx.z * gridDim.x + blockIdx.x : blockIdx.x;
+    const int u = xcd_item(w, nwg);
+    const int t = flat ? u % (int)gridDim.x : u;
+    const int z = flat ? u / (int)gridDim.x : (int)blockIdx.z;
     int64_t tm, tn;
     if (LOWER) {
         if (g.group > 1) grouped_lower_tile(t, (g.M + BM - 1) / BM, g.group, tm, tn);
@@ -57,7 +65,7 @@ gemm_kernel(GemmArgs g)
     gb.A = (const TI*)g.A + blockIdx.y * g.bsA;
     gb.B = (const TI*)g.B + blockIdx.y * g.bsB;
     gb.C = g.C + blockIdx.y * g.bsC;
-    gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(gb, tm, tn, blockIdx.z, lds);
+    gemm_tile<TI, BM, BN, BK, WM, WN, AKM, BNK, EPI, LOWER>(gb, tm, tn, __builtin_amdgcn_readfirstlane(z), lds);
 }
 
 // Row panels kept per XCD by the grouped tile order: as many BM-row panels

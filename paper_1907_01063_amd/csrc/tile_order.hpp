@@ -32,6 +32,16 @@ __host__ __device__ inline void lower_tile(int64_t b, int64_t& ti, int64_t& tj)
     tj = b - t * (t + 1) / 2;
 }
 
+// Work item of dispatch index w of a launch of nwg workgroups.  Workgroups
+// are dealt to the 8 XCDs round-robin (dispatch index mod 8); the item of w
+// is numbered so that XCD x takes the x-th contiguous range of items (a tail
+// past the last multiple of 8 keeps its own index).
+__host__ __device__ inline int xcd_item(int w, int nwg)
+{
+    const int per = nwg / 8;
+    return w < per * 8 ? (w % 8) * per + w / 8 : w;
+}
+
 // Tile (tm, tn) of index t of a tilesM x tilesN grid in the grouped order
 // (bands of G rows; a last, shorter band takes the remaining rows).
 __host__ __device__ inline void grouped_tile(int64_t t, int64_t tilesM, int64_t tilesN, int64_t G, int64_t& tm,

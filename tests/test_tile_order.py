@@ -1,7 +1,8 @@
 """Host check of the products' grouped tile orders (csrc/tile_order.hpp): for
 many grid shapes and band heights every index maps to a distinct tile of the
-grid (or of its lower triangle), and the tiles of one band come column by
-column.  Compiled with the host compiler; no GPU."""
+grid (or of its lower triangle), the tiles of one band come column by
+column, and the renumbering of dispatch indices by XCD is a bijection.
+Compiled with the host compiler; no GPU."""
 import os
 import subprocess
 
@@ -53,6 +54,19 @@ int main() {
             if ((int64_t)seen.size() != T) ++bad;
             ++cases;
         }
+    // the XCD renumbering is a bijection, each XCD's items contiguous
+    for (int nwg = 1; nwg <= 700; ++nwg) {
+        std::set<int> items;
+        for (int w = 0; w < nwg; ++w) {
+            const int u = xcd_item(w, nwg);
+            if (u < 0 || u >= nwg) ++bad;
+            items.insert(u);
+            const int per = nwg / 8;
+            if (w < per * 8 && u / per != w % 8) ++bad;   // XCD w mod 8 holds range w mod 8
+        }
+        if ((int)items.size() != nwg) ++bad;
+        ++cases;
+    }
     printf("%ld %ld\n", cases, bad);
     return bad != 0;
 }
