@@ -142,9 +142,12 @@ hipError_t gemm_f64(hipStream_t s, TileCfg cfg, bool a_km, bool b_nk, Epi epi, b
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, false, false, EPI_SUB, false)
     GPC_GEMM_CASE(double, TILE_128, 128, 128, 16, true, false, EPI_PARTIAL, false)
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, true, false, EPI_PARTIAL, false)
-    // panel solves with twice the workgroups (64-row tiles spanning all N)
+    // panel solves with twice the workgroups (64-row tiles spanning all N).
+    // The reverse sweep's (B stored K x N) takes k-chunks of 32: its 100 KB of
+    // LDS keep its workgroups off CUs that the side stream's products hold,
+    // which pace the sweep
     GPC_GEMM_CASE(double, TILE_64W, 64, 128, 16, false, true, EPI_STORE, false)
-    GPC_GEMM_CASE(double, TILE_64W, 64, 128, 16, false, false, EPI_STORE, false)
+    GPC_GEMM_CASE(double, TILE_64W, 64, 128, 32, false, false, EPI_STORE, false)
     // skinny narrow update (more, smaller tiles)
     GPC_GEMM_CASE(double, TILE_64, 64, 64, 16, false, true, EPI_SUB, false)
     // diagonal-block reverse step

@@ -29,7 +29,9 @@ import oracle
 import workloads as W
 from gpu_util import TOL, dev, host, progress, relf, say
 
-pytestmark = pytest.mark.gpu
+# the host oracle at n = 16384 takes one to three minutes, depending on the
+# host's cores: this module's tests get a longer time limit than the rest
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
 
 def oracle_run(case):
