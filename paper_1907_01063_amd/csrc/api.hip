@@ -614,7 +614,7 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
         // the first diagonal steps, not after the last one
         GPC_HIP(h, zero_strict_upper(s2, n, A, lda));
     }
-    // events: 1 + 2t = panel(t), 2 + 2t = big(t)
+    // events: 1 + 2t = panel and narrow update of step t done, 2 + 2t = big(t)
     auto ev_panel = [&](int64_t t) { return sync_event(h, 1 + 2 * (size_t)t); };
     auto ev_big = [&](int64_t t) { return sync_event(h, 2 + 2 * (size_t)t); };
     if (la && (!ev_panel(steps) || !ev_big(steps))) return GPC_ERR_HIP;
@@ -687,14 +687,8 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
             }
             return GPC_OK;
         };
-        if (la) {
-            GPC_HIP(h, hipEventRecord(ev_panel(t), s));
-            GPC_HIP(h, hipStreamWaitEvent(s2, ev_panel(t), 0));
-            st = big(s2);
-            if (st != GPC_OK) return st;
-            GPC_HIP(h, hipEventRecord(ev_big(t), s2));
-            if (t >= 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(t - 1), 0));
-        }
+        // the next block's columns were last written by big(t-1)
+        if (la && t >= 1) GPC_HIP(h, hipStreamWaitEvent(s, ev_big(t - 1), 0));
         {
             Traced tr(h, GPC_K_TRAILING_NARROW, 2.0 * dkB * (dmb * dnB + dnB * (dnB + 1.0) / 2.0),
                       (mixed ? 4.0 : 8.0) * (double)m2 * dkB + 16.0 * (double)m2 * dnB);
@@ -710,7 +704,17 @@ gpc_status factor_impl(gpc_handle* h, int64_t n, double* A, int64_t lda, int32_t
                 GPC_HIP(h, gemm_f64(s, skinny_tile(m2, nB), false, true, EPI_SUB, false, ng, 1));
             }
         }
-        if (!la) {
+        if (la) {
+            // big(t) needs only this step's panel, but starts after the
+            // narrow update: the narrow update, which the next block's chain
+            // waits for, then has the CUs to itself, and big(t) runs beside
+            // that chain instead
+            GPC_HIP(h, hipEventRecord(ev_panel(t), s));
+            GPC_HIP(h, hipStreamWaitEvent(s2, ev_panel(t), 0));
+            st = big(s2);
+            if (st != GPC_OK) return st;
+            GPC_HIP(h, hipEventRecord(ev_big(t), s2));
+        } else {
             st = big(s);
             if (st != GPC_OK) return st;
         }
