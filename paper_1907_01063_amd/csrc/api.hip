@@ -564,11 +564,12 @@ gpc_status gpc_get_options(const gpc_handle* h, gpc_options* o)
 // block's columns ("narrow", main stream) and the rest ("big", lower tiles
 // only).  With lookahead the big update of step t
 // runs on a second stream while step t+1's diagonal and panel work proceeds:
-//   main: wait big(t-2); panels(t); record panel(t); wait big(t-1); narrow(t)
+//   main: wait big(t-2); panels(t); wait big(t-1); narrow(t); record panel(t)
 //   side: wait panel(t); big(t); record big(t)
 // (panels(t) touch columns no big(t-1) writes; narrow(t) writes columns
-// big(t-1) writes; FP32 panel copies of the mixed form are double-buffered
-// by step parity, freed by the same waits.)  The strict upper triangle is
+// big(t-1) writes; big(t) needs only panels(t), but starts after narrow(t),
+// which the next step's chain waits for; FP32 panel copies of the mixed form
+// are double-buffered by step parity, freed by the same waits.)  The strict upper triangle is
 // zeroed: with lookahead on the side stream before its first big update,
 // else after the last step.
 namespace {
